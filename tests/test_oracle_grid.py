@@ -1,0 +1,156 @@
+"""Whole-grid pins of the oracle: S2O4 amplification, uniform-flow
+preservation, conservation, symmetry, density-wave convergence, the TGV
+statistics at t = 0 and the paper's printed time steps."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2207_01173_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_s2o4_amplification_polynomial(oracle):
+    """P8: on q' = lam q with exact L and dL/dt, Eq. (two-stage) multiplies by
+    1 + z + z^2/2 + z^3/6 + z^4/24, z = lam dt (classical RK4's polynomial)."""
+    for z in [-0.3, 0.1, -1.7, 0.9, -2.5]:
+        got = oracle.s2o4_scalar(1.0, z, 1.0)
+        ref = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+        assert abs(got - ref) <= 1e-15 * max(1.0, abs(ref))
+
+
+def test_s2o4_fourth_order_on_nonlinear_ode(oracle):
+    """The scalar S2O4 recursion is fourth order on q' = lam q over a unit interval."""
+    errs = []
+    for n in (10, 20, 40):
+        q, dt = 1.0, 1.0 / n
+        for _ in range(n):
+            q = oracle.s2o4_scalar(q, -1.3, dt)
+        errs.append(abs(q - math.exp(-1.3)))
+    assert math.log(errs[1] / errs[2], 2) > 3.9
+
+
+def _uniform(n, rho=1.3, U=0.3, V=-0.2, Wv=0.1, p=2.0):
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    return np.ascontiguousarray(W.conserved(f(rho), f(U), f(V), f(Wv), f(p)))
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (7, 9, 6)])
+def test_uniform_flow_bitwise(oracle, n):
+    """P10: every face sees identical inputs, so a uniform state is preserved bitwise."""
+    p = W.tgv_params(n)
+    q = _uniform(n)
+    q2, _ = oracle.step(p, q, 3, 1e-2)
+    np.testing.assert_array_equal(q2, q)
+
+
+def test_periodic_conservation(oracle):
+    """P11: totals of mass, momentum and energy drift by round-off only."""
+    p = W.tgv_params((12, 10, 8), ma=0.3, re=200.0)
+    p["mu_ref"] = 2e-3
+    q = W.smooth_random(p, seed=5)
+    dv = np.prod([(p["hi"][d] - p["lo"][d]) / p["n"][d] for d in range(3)])
+    scale = np.abs(q).sum(axis=(1, 2, 3)) * dv
+    tot0 = q.sum(axis=(1, 2, 3)) * dv
+    q2, _ = oracle.step(p, q, 4, 0.0)
+    tot1 = q2.sum(axis=(1, 2, 3)) * dv
+    assert (np.abs(tot1 - tot0) <= 1e-13 * scale).all(), (tot1 - tot0) / scale
+    assert np.abs(q2 - q).max() > 1e-4  # the flow did change
+
+
+def _rotate(q):
+    """Cyclic relabelling of axes: new (x, y, z) = old (z, x, y); velocity
+    components follow.  q[c, z, y, x] -> q'[c, z', y', x']."""
+    r = q.transpose(0, 2, 3, 1)
+    return np.ascontiguousarray(r[[0, 3, 1, 2, 4]])
+
+
+def test_rotation_equivariance(oracle):
+    """P15: stepping a cyclically relabelled field equals relabelling the stepped field."""
+    p = W.tgv_params((10, 8, 6), ma=0.3, re=300.0)
+    q = W.smooth_random(p, seed=9)
+    pr = dict(p)
+    pr["n"] = (p["n"][2], p["n"][0], p["n"][1])
+    a, _ = oracle.step(p, q, 2, 0.02)
+    b, _ = oracle.step(pr, _rotate(q), 2, 0.02)
+    err = np.abs(b - _rotate(a)).max(axis=(1, 2, 3)) / np.abs(a).max(axis=(1, 2, 3))
+    assert (err <= 2e-14).all(), err
+
+
+def test_mirror_equivariance(oracle):
+    """Reflecting x -> -x (cells reversed, x-momentum negated) commutes with a
+    step: pins the left/right roles and the slope signs of the reconstruction."""
+    p = W.tgv_params((10, 8, 6), ma=0.3, re=300.0)
+    q = W.smooth_random(p, seed=13)
+
+    def mirror(a):
+        m = np.ascontiguousarray(a[:, :, :, ::-1])
+        m[1] *= -1
+        return m
+
+    a, _ = oracle.step(p, q, 2, 0.02)
+    b, _ = oracle.step(p, mirror(q), 2, 0.02)
+    err = np.abs(b - mirror(a)).max(axis=(1, 2, 3)) / np.abs(a).max(axis=(1, 2, 3))
+    assert (err <= 2e-14).all(), err
+
+
+def test_tgv_initial_statistics(oracle):
+    """P13: point-value TGV at t = 0: E_k = 1/8 (the density correction averages
+    out on the grid) and eps = (mu/rho0) 3/4 kappa(h)^2 with the fourth-order
+    central difference's symbol kappa(h) = (8 sin h - sin 2h)/(6h); no dilatation."""
+    for n in (16, 32):
+        p = W.tgv_params(n)
+        q = W.tgv_initial(p)
+        s = oracle.stats(p, q, rho0=1.0)
+        h = 2 * math.pi / n
+        kap = (8 * math.sin(h) - math.sin(2 * h)) / (6 * h)
+        assert abs(s["Ek"] - 0.125) <= 1e-12
+        assert abs(s["eps_com"] - p["mu_ref"] * 0.75 * kap * kap) <= 1e-12 * p["mu_ref"]
+        assert abs(s["eps_dil"]) <= 1e-16
+    # the 32^3 value quoted with the statistics definition (4.687038e-4)
+    p = W.tgv_params(32)
+    assert abs(oracle.stats(p, W.tgv_initial(p))["eps_com"] - 4.687038e-4) < 5e-11
+
+
+def _read_table3():
+    rows = []
+    with open(os.path.join(GOLDEN, "table3_dt.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, dt, sig = line.split()
+                rows.append((int(n), float(dt), int(sig)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _read_table3(), ids=lambda r: str(r[0]))
+def test_table3_time_steps(oracle, row):
+    """P14: the CFL rule (R13) at CFL 0.4 reproduces every printed Table 3 time
+    step of the TGV on [-pi, pi]^3 at Ma = 0.1."""
+    n, printed, sig = row
+    p = W.tgv_params(n, ma=0.1, lo=-math.pi, hi=math.pi, cfl=0.4)
+    q = W.tgv_initial(p)
+    dt = oracle.cfl_dt(p, q)
+    assert float(f"{dt:.{sig - 1}e}") == printed, dt
+
+
+def test_density_wave_convergence(oracle):
+    """P12: Euler (tau = 0) advection of a density wave along (1,1,1); the
+    cell-average error against the exact solution converges at high order."""
+    t_end = 0.25
+    errs = []
+    for n in (8, 16, 32):
+        p = W.density_wave_params(n, cfl=0.5)
+        q = W.density_wave_initial(p)
+        h = 2.0 / n
+        dt0 = 0.5 * h / (1.0 + math.sqrt(1.4 / 0.8))
+        nsteps = int(math.ceil(t_end / dt0))
+        q2, _ = oracle.step(p, q, nsteps, t_end / nsteps)
+        exact = W.density_wave_cell_average(p, t_end)
+        errs.append((np.abs(q2[0] - exact).mean(), np.abs(q2[0] - exact).max()))
+    o1 = [math.log(errs[i][0] / errs[i + 1][0], 2) for i in range(2)]
+    oinf = [math.log(errs[i][1] / errs[i + 1][1], 2) for i in range(2)]
+    print("density wave L1/Linf errors", errs, "orders", o1, oinf)
+    assert o1[-1] >= 3.7 and oinf[-1] >= 3.7, (o1, oinf)
