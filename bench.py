@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the HGKS hot path on one MI355X: cell-stage updates/s of the
+Taylor-Green vortex at 256^3 (Ma 0.29, Re 1600, Pr 0.72, CFL 0.5), every step
+a full S2O4 step (two stages, each: three directions of reconstruction and
+flux, then the cell update; CFL time step reduced on the device).
+
+Prints one JSON line.  `roofline` reports the dominant kernel (the flux
+kernel: second tangential sweep, Gauss-point BGK flux, face assembly) against
+the FP64 vector ALU peak, with its duration measured by HIP events on the
+library's stream over the timed region.  `cpu_baseline` times the oracle
+(plain FP64 CPU implementation) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-stage updates/s, 256^3 TGV: FP64 vs mixed-FP32 at stated error; % HBM roofline"
+UNIT = "cell-stage updates/s"
+
+# Floating-point operations of the method per face, counted once (no halo
+# recomputation) by the oracle's counting scalar (oracle.count_flops(); kept in
+# step with it by tests/test_bench_constants.py): second tangential sweep plus
+# Gauss-point flux for 4 Gauss points, plus the face assembly.  Every add,
+# multiply, divide, square root and transcendental counts as one operation.
+FLOPS_FLUX_PER_FACE = 66491.0
+# normal sweep plus first tangential sweep (2 Gauss lines) per face
+FLOPS_RECON_PER_FACE = 6630.0
+
+# MI355X published peaks
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def tgv_workload(n: int):
+    from paper_2207_01173_amd import workloads as W
+
+    return W.tgv_params(n, ma=0.29, re=1600.0, pr=0.72, cfl=0.5)
+
+
+def cpu_baseline(n_sample: int = 64, steps: int = 1) -> dict:
+    """The oracle, as it stands, on the host cores: S2O4 steps of a TGV of the
+    same physics at a smaller grid (the per-cell work does not depend on the
+    grid size)."""
+    from oracle import oracle as O
+    from paper_2207_01173_amd import workloads as W
+
+    p = tgv_workload(n_sample)
+    q = W.tgv_initial(p)
+    O.lib()
+    t0 = time.perf_counter()
+    O.step(p, q, steps, 0.0)
+    t1 = time.perf_counter()
+    cs = 2.0 * n_sample ** 3 * steps
+    return {
+        "value": cs / (t1 - t0),
+        "unit": UNIT,
+        "cores": O.get_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} S2O4 step(s) of the {n_sample}^3 TGV (Ma 0.29, Re 1600, Pr 0.72, CFL 0.5), "
+                  f"{cs:.0f} cell-stages in {t1 - t0:.2f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab-decomposition design is described, not built); run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2207_01173_amd import hgks
+    from paper_2207_01173_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.n
+    p = tgv_workload(n)
+    prec = hgks.FP64 if args.precision == "fp64" else hgks.MIXED
+    print(f"# building TGV {n}^3 initial state", file=sys.stderr, flush=True)
+    q0 = W.tgv_initial(p)
+    solver = hgks.Solver(p, q0, precision=prec)
+    del q0
+
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    solver.step(args.warmup, 0.0)
+    torch.cuda.synchronize()
+
+    hgks.hgks_profile(solver.ctx, True)
+    hgks.hgks_profile_read(solver.ctx)  # clear
+    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(args.steps, 0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = hgks.hgks_profile_read(solver.ctx)
+    hgks.hgks_profile(solver.ctx, False)
+    st = solver.stats()
+    if st["nonfinite"] or not (st["min_p"] > 0):
+        print("# state became invalid during the benchmark", file=sys.stderr)
+        return 1
+
+    elapsed = t1 - t0
+    cell_stages = 2.0 * n ** 3 * args.steps
+    value = cell_stages / elapsed
+
+    flux_ms, flux_n = prof["flux"]
+    faces_per_launch = (n + 1) * n * n
+    flux_avg_s = flux_ms / flux_n / 1e3
+    achieved = FLOPS_FLUX_PER_FACE * faces_per_launch / flux_avg_s / 1e12
+    peak = PEAK_FP64_VECTOR_TFLOPS if prec == hgks.FP64 else PEAK_FP32_VECTOR_TFLOPS
+    roofline = {
+        "bound": "alu",
+        "kernel": "flux_kernel (2nd tangential WENO-Z sweep + Gauss-point BGK flux + face assembly)",
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "avg_launch_ms": round(flux_ms / flux_n, 4),
+        "flops_per_face": FLOPS_FLUX_PER_FACE,
+        "faces_per_launch": faces_per_launch,
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == hgks.FP64 else "f32-recon-flux/f64-state",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Taylor-Green vortex {n}^3 periodic on [0,2pi]^3, Ma 0.29, Re 1600, Pr 0.72, "
+                        f"CFL 0.5 (CFL time step each step)",
+            "n": n,
+            "precision": args.precision,
+            "parallelism": "single GPU",
+            "simulated_time": st["t"],
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    solver.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,146 @@
+/*
+ * hgks.h - C ABI of the MI355X (gfx950) high-order gas-kinetic scheme hot path.
+ *
+ * The library advances cell-averaged conserved variables
+ * Q = (rho, rho U, rho V, rho W, rho E) on a 3D structured box grid with the
+ * high-order gas-kinetic scheme of arXiv 2207.01173, Sec. 2:
+ *   - fifth-order WENO-Z reconstruction, dimension by dimension, of values and
+ *     normal/tangential slopes at the 2x2 Gauss points of every cell face;
+ *   - the time-dependent BGK gas distribution at each Gauss point, Eq. (flux),
+ *     with the equilibrium from the compatibility condition and tau = mu/p;
+ *   - the time-integrated flux over [0, dt] and [0, dt/2], giving the flux and
+ *     its time derivative, Eq. (expansion-1);
+ *   - the two-stage fourth-order update, Eq. (two-stage);
+ *   - ghost cells synthesised on the fly (periodic, or an isothermal no-slip
+ *     wall on the y axis), the CFL time step, and volume statistics
+ *     (kinetic energy and viscous dissipation, Sec. 4.1).
+ *
+ * Memory: every device pointer is caller-owned (allocated by the caller, e.g.
+ * through PyTorch).  The state array q_dev is float64 SoA [5][nz][ny][nx],
+ * x fastest, and always holds the latest state once the stream has drained.
+ * The workspace is an opaque device buffer of hgks_workspace_size() bytes,
+ * 256-byte aligned.  The library allocates only its host-side context.
+ *
+ * Streams: all device work of a context is enqueued on the hipStream_t given
+ * to hgks_init (passed as void*).  hgks_step is asynchronous; hgks_stats,
+ * hgks_dt and hgks_residual synchronise that stream before returning.
+ *
+ * Errors: functions return an hgks_status.  Argument and configuration errors
+ * are detected before any device work (HGKS_E_INVALID).  A HIP runtime error
+ * returns HGKS_E_DEVICE; the detail text is available from hgks_last_error().
+ * A non-finite or non-positive density/pressure found by hgks_stats is latched
+ * and returned by the following hgks_step (HGKS_E_NONFINITE /
+ * HGKS_E_NEGATIVE_STATE) without advancing.
+ *
+ * Threads: a context must not be used from two threads at once; distinct
+ * contexts are independent.
+ */
+#ifndef HGKS_H
+#define HGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HGKS_ABI_VERSION 1
+
+typedef struct hgks_ctx_s* hgks_ctx;
+
+typedef enum {
+  HGKS_OK = 0,
+  HGKS_E_INVALID = 1,        /* bad argument, configuration or workspace size */
+  HGKS_E_NOMEM = 2,          /* host allocation failed */
+  HGKS_E_DEVICE = 3,         /* HIP runtime error (see hgks_last_error) */
+  HGKS_E_NONFINITE = 4,      /* the state holds NaN or Inf */
+  HGKS_E_NEGATIVE_STATE = 5, /* density or pressure <= 0 somewhere */
+  HGKS_E_UNSUPPORTED = 6     /* valid request this build does not provide */
+} hgks_status;
+
+enum { HGKS_BC_PERIODIC = 0, HGKS_BC_ISOTHERMAL_WALL = 1 }; /* wall: y axis only */
+enum { HGKS_FP64 = 0, HGKS_MIXED = 1 };
+
+typedef struct {
+  int32_t abi_version;   /* must equal HGKS_ABI_VERSION */
+  int32_t n[3];          /* interior cells nx, ny, nz; each >= 4 */
+  double lo[3], hi[3];   /* physical box; y walls (if any) at lo[1], hi[1] */
+  int32_t bc[3];         /* HGKS_BC_* per axis; a wall only on axis 1 */
+  double y_stretch;      /* tanh stretching b of the y axis (Sec. 4.2 map); 0: uniform */
+  double gamma;          /* specific heat ratio, 1 < gamma <= 5/3 */
+  double prandtl;        /* Prandtl number (heat-flux correction when != 1) */
+  double mu_ref, T_ref, mu_exp; /* mu = mu_ref (T/T_ref)^mu_exp, T = p/rho */
+  double T_wall;         /* isothermal wall temperature (p/rho units) */
+  double body_force[3];  /* constant acceleration (source in L) */
+  double cfl;            /* CFL number of the time-step rule when dt is not fixed */
+  double rho_ref;        /* rho0 of the statistics normalisation (> 0) */
+  int32_t precision;     /* HGKS_FP64 or HGKS_MIXED */
+  int32_t flags;         /* reserved, must be 0 */
+} hgks_config;
+
+typedef struct {
+  double t;              /* simulated time since hgks_init's t0 origin */
+  double dt_last;        /* last time step used */
+  int64_t steps;         /* steps taken since hgks_init */
+  double Ek;             /* (1/(rho0 Omega)) int rho |U|^2 / 2 */
+  double eps_sol;        /* (mu_ref/(rho0 Omega)) int omega . omega */
+  double eps_dil;        /* (4/3)(mu_ref/(rho0 Omega)) int (div U)^2 */
+  double eps_com;        /* eps_sol + eps_dil (Sec. 4.1 total viscous dissipation) */
+  double total[5];       /* int Q dV */
+  double max_abs[5];     /* max |Q| per component */
+  double min_p, min_rho; /* minima of pressure and density */
+  int32_t nonfinite;     /* 1 if any NaN/Inf was found */
+  int32_t pad_;
+} hgks_stats_t;
+
+/* Workspace bytes for a configuration.  Errors: HGKS_E_INVALID. */
+hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes);
+
+/* Create a context over caller-owned memory: q_dev (state, in/out), ws_dev
+ * (>= hgks_workspace_size bytes, 256-byte aligned) and a HIP stream (NULL:
+ * the default stream).  t0 is the initial simulated time.  Enqueues the
+ * geometry upload and the first wave-speed reduction on the stream. */
+hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_t ws_bytes,
+                      void* hip_stream, double t0, hgks_ctx* out);
+
+/* Advance nsteps S2O4 steps (Eq. (two-stage)).  dt_fixed > 0 uses that time
+ * step; dt_fixed <= 0 takes dt = cfl / max_cells max_d (|U_d| + c) / h_d from
+ * the state at the start of each step.  Asynchronous. */
+hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed);
+
+/* Statistics of the current state (synchronises the stream). */
+hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out);
+
+/* CFL time step of the current state (synchronises the stream). */
+hgks_status hgks_dt(hgks_ctx ctx, double* dt_out);
+
+/* L(Q) and dL/dt (Eq. (semi2) and its time derivative) of an arbitrary state
+ * q_dev (same layout as the context's state) with flux windows [0, dt] and
+ * [0, dt/2]; outputs L_dev, dL_dev in the same layout.  Uses the context's
+ * workspace; synchronises the stream. */
+hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* L_dev, double* dL_dev);
+
+/* Kernel timing for benchmarks, with HIP events recorded on the context's
+ * stream.  enable != 0: every kernel launch made by hgks_step is bracketed by
+ * a pair of events.  hgks_profile_read synchronises the stream and returns,
+ * per kernel class, the summed milliseconds and launch counts since the last
+ * read, then resets them.  Classes: 0 reconstruction (normal and first
+ * tangential sweep), 1 flux (second tangential sweep, Gauss-point flux,
+ * face assembly), 2 cell update, 3 other.  Errors: HGKS_E_INVALID,
+ * HGKS_E_DEVICE. */
+#define HGKS_PROFILE_CLASSES 4
+hgks_status hgks_profile(hgks_ctx ctx, int32_t enable);
+hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int64_t launches[HGKS_PROFILE_CLASSES]);
+
+/* Release the host context (device memory stays the caller's). */
+hgks_status hgks_destroy(hgks_ctx ctx);
+
+const char* hgks_status_string(hgks_status s);
+const char* hgks_last_error(hgks_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGKS_H */

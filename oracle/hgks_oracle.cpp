@@ -713,6 +713,26 @@ static Gas<double> gas_of(const Config& c) {
   return g;
 }
 
+/* 2x2 Gauss quadrature (weights 1/4 of the face area) of the Gauss-point
+ * integrals S1 = sum F(dt), S2 = sum F(dt/2); then F^n = (4 I(dt/2) - I(dt))/dt
+ * and dF^n/dt = 4 (I(dt) - 2 I(dt/2))/dt^2 (Eq. (expansion-1)); momentum
+ * rotated back from the local frame of direction d.  out[10]: F^n, dF^n/dt. */
+static void face_assembly(const double S1[5], const double S2[5], double area, double dt, int d, double out[10]) {
+  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+  double Fn[5], dF[5];
+  for (int k = 0; k < 5; ++k) {
+    double I1 = 0.25 * area * S1[k];  // integral over [0, dt]
+    double I2 = 0.25 * area * S2[k];  // integral over [0, dt/2]
+    Fn[k] = (4.0 * I2 - I1) / dt;
+    dF[k] = 4.0 * (I1 - 2.0 * I2) / (dt * dt);
+  }
+  const int gc[5] = {0, 1 + d, 1 + d1, 1 + d2, 4};
+  for (int k = 0; k < 5; ++k) {
+    out[gc[k]] = Fn[k];
+    out[5 + gc[k]] = dF[k];
+  }
+}
+
 /* Face fluxes of direction d for the whole grid.
  * Output fl[(f * N1 + a) * N2 + b][10]: F^n (5) and dF^n/dt (5), integrated over
  * the face, momentum in the global frame.  f = 0..n_d (face between cells f-1, f). */
@@ -773,27 +793,36 @@ static void direction_fluxes(const Grid& g, const std::vector<double>& pad, int 
               }
             }
           }
-          /* 2x2 Gauss quadrature, weights 1/4 of the face area */
-          double area = g.h[d1][a] * g.h[d2][b];
-          double Fn[5], dF[5];
-          for (int k = 0; k < 5; ++k) {
-            double I1 = 0.25 * area * S1[k];  // integral over [0, dt]
-            double I2 = 0.25 * area * S2[k];  // integral over [0, dt/2]
-            Fn[k] = (4.0 * I2 - I1) / dt;
-            dF[k] = 4.0 * (I1 - 2.0 * I2) / (dt * dt);
-          }
-          /* rotate momentum back to the global frame */
-          double* o = &fl[(((size_t)f * N1 + a) * N2 + b) * 10];
-          double gF[5], gD[5];
-          gF[0] = Fn[0]; gD[0] = dF[0];
-          gF[4] = Fn[4]; gD[4] = dF[4];
-          gF[1 + d] = Fn[1]; gD[1 + d] = dF[1];
-          gF[1 + d1] = Fn[2]; gD[1 + d1] = dF[2];
-          gF[1 + d2] = Fn[3]; gD[1 + d2] = dF[3];
-          for (int k = 0; k < 5; ++k) { o[k] = gF[k]; o[5 + k] = gD[k]; }
+          face_assembly(S1, S2, g.h[d1][a] * g.h[d2][b], dt, d, &fl[(((size_t)f * N1 + a) * N2 + b) * 10]);
         }
     }
   }
+}
+
+/* L and dL/dt of cell (i,j,k) from the integrated fluxes of its six faces
+ * (Eq. (semi2)), with the body-force source (R19): S = (0, rho f, m . f),
+ * dS/dt = (0, f L_rho, f . L_m).                                             */
+static void cell_residual(const Grid& g, const double* q, int i, int j, int k, const double* fm[3],
+                          const double* fp[3], double l[5], double dl[5]) {
+  const double* f = g.c.body_force;
+  double vol = g.h[0][i] * g.h[1][j] * g.h[2][k];
+  for (int c = 0; c < 5; ++c) { l[c] = 0.0; dl[c] = 0.0; }
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 5; ++c) {
+      l[c] -= (fp[d][c] - fm[d][c]) / vol;
+      dl[c] -= (fp[d][5 + c] - fm[d][5 + c]) / vol;
+    }
+  double rho = q[sidx(g, 0, i, j, k)];
+  double m[3] = {q[sidx(g, 1, i, j, k)], q[sidx(g, 2, i, j, k)], q[sidx(g, 3, i, j, k)]};
+  double lrho = l[0];
+  double lm[3];
+  for (int a = 0; a < 3; ++a) {
+    l[1 + a] += rho * f[a];
+    lm[a] = l[1 + a];
+  }
+  l[4] += m[0] * f[0] + m[1] * f[1] + m[2] * f[2];
+  for (int a = 0; a < 3; ++a) dl[1 + a] += f[a] * lrho;
+  dl[4] += f[0] * lm[0] + f[1] * lm[1] + f[2] * lm[2];
 }
 
 /* L(Q) and dL/dt (Eq. (semi2) and its time derivative) with the body-force
@@ -803,41 +832,90 @@ static void residual(const Grid& g, const double* q, double dt, double* L, doubl
   fill_padded(g, q, pad);
   std::vector<double> fl[3];
   for (int d = 0; d < 3; ++d) direction_fluxes(g, pad, d, dt, fl[d]);
-  const double* f = g.c.body_force;
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
-        double vol = g.h[0][i] * g.h[1][j] * g.h[2][k];
-        double l[5] = {0, 0, 0, 0, 0}, dl[5] = {0, 0, 0, 0, 0};
-        int ijk[3] = {i, j, k};
+        double l[5], dl[5];
+        const double* fm[3];
+        const double* fp[3];
         for (int d = 0; d < 3; ++d) {
-          int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-          int N1 = g.n[d1], N2 = g.n[d2];
-          int nn = ijk[d], a = ijk[d1], b = ijk[d2];
-          const double* fm = &fl[d][(((size_t)nn * N1 + a) * N2 + b) * 10];
-          const double* fp = &fl[d][(((size_t)(nn + 1) * N1 + a) * N2 + b) * 10];
-          for (int c = 0; c < 5; ++c) {
-            l[c] -= (fp[c] - fm[c]) / vol;
-            dl[c] -= (fp[5 + c] - fm[5 + c]) / vol;
-          }
+          int d1 = (d + 1) % 3, d2 = (d + 2) % 3, ijk[3] = {i, j, k};
+          size_t N1 = g.n[d1], N2 = g.n[d2];
+          fm[d] = &fl[d][(((size_t)ijk[d] * N1 + ijk[d1]) * N2 + ijk[d2]) * 10];
+          fp[d] = &fl[d][(((size_t)(ijk[d] + 1) * N1 + ijk[d1]) * N2 + ijk[d2]) * 10];
         }
-        double rho = q[sidx(g, 0, i, j, k)];
-        double m[3] = {q[sidx(g, 1, i, j, k)], q[sidx(g, 2, i, j, k)], q[sidx(g, 3, i, j, k)]};
-        double lrho = l[0];
-        double lm[3];
-        for (int a = 0; a < 3; ++a) {
-          l[1 + a] += rho * f[a];
-          lm[a] = l[1 + a];
-        }
-        l[4] += m[0] * f[0] + m[1] * f[1] + m[2] * f[2];
-        for (int a = 0; a < 3; ++a) dl[1 + a] += f[a] * lrho;
-        dl[4] += f[0] * lm[0] + f[1] * lm[1] + f[2] * lm[2];
+        cell_residual(g, q, i, j, k, fm, fp, l, dl);
         for (int c = 0; c < 5; ++c) {
           L[sidx(g, c, i, j, k)] = l[c];
           dL[sidx(g, c, i, j, k)] = dl[c];
         }
       }
+}
+
+/* Integrated flux of the single face (f, a, b) of direction d, from scratch:
+ * the same normal sweep, tangential sweeps, Gauss-point fluxes and assembly as
+ * direction_fluxes, restricted to the 5x5 patch of faces this face needs.     */
+static void single_face_flux(const Grid& g, const std::vector<double>& pad, int d, int f, int a, int b, double dt,
+                             double out[10]) {
+  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+  const Gas<double> gas = gas_of(g.c);
+  double A[5][5][N_COUNT][5];  // [t1 offset][t2 offset]
+  for (int ja = 0; ja < 5; ++ja)
+    for (int jb = 0; jb < 5; ++jb) {
+      double cells[6][5];
+      for (int m = 0; m < 6; ++m) local_q(g, pad, d, f - 3 + m, a - 2 + ja, b - 2 + jb, cells[m]);
+      for (int k = 0; k < 5; ++k) {
+        double c6[6];
+        for (int m = 0; m < 6; ++m) c6[m] = cells[m][k];
+        double* o = &A[ja][jb][0][0];
+        normal_sweep(c6, o[N_QL * 5 + k], o[N_QR * 5 + k], o[N_DLN * 5 + k], o[N_DRN * 5 + k], o[N_D0 * 5 + k]);
+      }
+    }
+  double Bt[5][2][T_COUNT][5];  // [t2 offset][g1]
+  for (int jb = 0; jb < 5; ++jb) {
+    double in[5][N_COUNT][5];
+    for (int j = 0; j < 5; ++j) std::memcpy(in[j], A[j][jb], sizeof(in[j]));
+    for (int g1 = 0; g1 < 2; ++g1) tangential_sweep_1(in, 1 + g1, Bt[jb][g1]);
+  }
+  double S1[5] = {0, 0, 0, 0, 0}, S2[5] = {0, 0, 0, 0, 0};
+  for (int g1 = 0; g1 < 2; ++g1) {
+    double in[5][T_COUNT][5];
+    for (int j = 0; j < 5; ++j) std::memcpy(in[j], Bt[j][g1], sizeof(in[j]));
+    for (int g2 = 0; g2 < 2; ++g2) {
+      GPInput<double> gp;
+      tangential_sweep_2(in, 1 + g2, gp);
+      double F1[5], F2[5];
+      gp_flux_scaled(gp, g.dface[d][f], g.dgp[d1][2 * a + g1], g.dgp[d2][2 * b + g2], gas, dt, F1, F2);
+      for (int k = 0; k < 5; ++k) {
+        S1[k] += F1[k];
+        S2[k] += F2[k];
+      }
+    }
+  }
+  face_assembly(S1, S2, g.h[d1][a] * g.h[d2][b], dt, d, out);
+}
+
+/* L and dL/dt at a list of cells only (six single-face fluxes each). */
+static void residual_at(const Grid& g, const double* q, double dt, int ncell, const int* ijk, double* L, double* dL) {
+  std::vector<double> pad;
+  fill_padded(g, q, pad);
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < ncell; ++c) {
+    const int i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
+    const int idx[3] = {i, j, k};
+    double fmv[3][10], fpv[3][10];
+    const double* fm[3];
+    const double* fp[3];
+    for (int d = 0; d < 3; ++d) {
+      const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+      single_face_flux(g, pad, d, idx[d], idx[d1], idx[d2], dt, fmv[d]);
+      single_face_flux(g, pad, d, idx[d] + 1, idx[d1], idx[d2], dt, fpv[d]);
+      fm[d] = fmv[d];
+      fp[d] = fpv[d];
+    }
+    cell_residual(g, q, i, j, k, fm, fp, &L[5 * c], &dL[5 * c]);
+  }
 }
 
 /* CFL time step (R13): dt = CFL / max_cells max_d (|U_d| + c) / h_d. */
@@ -1064,6 +1142,13 @@ void hgo_residual(const hgo_config* cfg, const double* q, double dt, double* L, 
   Grid g;
   build_grid(*cfg, g);
   residual(g, q, dt, L, dL);
+}
+/* L, dL/dt at ncell cells ijk[3 * c + (0,1,2)]; outputs L[5 * c + comp]. */
+void hgo_residual_at(const hgo_config* cfg, const double* q, double dt, int ncell, const int* ijk, double* L,
+                     double* dL) {
+  Grid g;
+  build_grid(*cfg, g);
+  residual_at(g, q, dt, ncell, ijk, L, dL);
 }
 double hgo_cfl_dt(const hgo_config* cfg, const double* q) {
   Grid g;

@@ -101,6 +101,7 @@ def lib():
         L.hgo_weno_linear.argtypes = [_D, i, _D]
         L.hgo_normal_sweep.argtypes = [_D, _D]
         L.hgo_residual.argtypes = [P, _D, d, _D, _D]
+        L.hgo_residual_at.argtypes = [P, _D, d, i, ctypes.POINTER(ctypes.c_int), _D, _D]
         L.hgo_cfl_dt.argtypes = [P, _D]
         L.hgo_cfl_dt.restype = d
         L.hgo_step.argtypes = [P, _D, i, d]
@@ -241,6 +242,18 @@ def residual(p: dict, q: np.ndarray, dt: float):
     q = _q(np.ascontiguousarray(q), cfg)
     L, dL = np.zeros_like(q), np.zeros_like(q)
     lib().hgo_residual(ctypes.byref(cfg), _ptr(q), float(dt), _ptr(L), _ptr(dL))
+    return L, dL
+
+
+def residual_at(p: dict, q: np.ndarray, dt: float, cells):
+    """L and dL/dt at the given cells [(i, j, k), ...] only; returns arrays [n, 5]."""
+    cfg = make_config(p)
+    q = _q(np.ascontiguousarray(q), cfg)
+    ijk = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+    n = ijk.shape[0]
+    L, dL = np.zeros((n, 5)), np.zeros((n, 5))
+    lib().hgo_residual_at(ctypes.byref(cfg), _ptr(q), float(dt), int(n),
+                          ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(L), _ptr(dL))
     return L, dL
 
 

@@ -1,0 +1,1032 @@
+// HGKS hot path for MI355X (gfx950): kernels and the C ABI declared in hgks.h.
+//
+// Per S2O4 stage and direction d (local frame (n, t1, t2) = (d, d+1, d+2)):
+//   recon_kernel<d>: normal WENO-Z sweep of a face tile (values and slopes of
+//     the left/right states and the equilibrium slope), staged in LDS, then
+//     the first tangential sweep to the two Gauss lines along t1 -> buffer B.
+//   flux_kernel<d>:  one lane per Gauss point: second tangential sweep along t2,
+//     the BGK flux of Eq. (flux) integrated over [0, dt] and [0, dt/2], the
+//     2x2 Gauss sum by cross-lane shuffles, F^n and dF^n/dt -> face buffer F_d.
+// then update_kernel<stage>: L, dL/dt from the six faces of each cell and the
+// two-stage update of Eq. (two-stage); stage 2 also reduces the wave speed of
+// the new state for the next CFL time step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hgks.h"
+#include "hgks_numerics.hpp"
+
+namespace hgks {
+
+// Quantities per face and Gauss line after the first tangential sweep.
+enum {
+  B_QL = 0, B_QR = 5, B_DLN = 10, B_DRN = 15, B_D0 = 20, B_DLT1 = 25, B_DRT1 = 30, B_COUNT = 35
+};
+
+struct Params {
+  int n[3];
+  int bc[3];
+  double gamma, gm1, K, mu_ref, T_ref, mu_exp, pr_fix, T_wall;
+  double force[3];
+  const double* hcell[3];  // cell widths
+  const double* dface[3];  // d(index)/dx at faces 0..n
+  const double* dgp[3];    // d(index)/dx at the Gauss points, 2 per cell
+  const double* dcen[3];   // d(index)/dx at cell centres
+};
+
+// Scalars kept on the device so that a step needs no host round trip.
+struct Scalars {
+  double dt;                 // time step of the current step
+  double t;                  // simulated time
+  double dt_residual;        // time step used by hgks_residual
+  double steps;              // steps taken
+  unsigned long long smax;   // bit pattern of max wave speed / h (positive double)
+  unsigned long long pad[3];
+};
+
+__host__ __device__ inline size_t cells(const Params& P) { return (size_t)P.n[0] * P.n[1] * P.n[2]; }
+
+// Face extents of direction d: one more face than cells along d.
+__host__ __device__ inline void face_extents(const Params& P, int d, int fe[3]) {
+  for (int a = 0; a < 3; ++a) fe[a] = P.n[a] + (a == d ? 1 : 0);
+}
+// Extents of buffer B of direction d: faces, plus two ghost rows on each side
+// of t2 when t2 is a wall axis (the second tangential sweep reads them).
+__host__ __device__ inline void b_extents(const Params& P, int d, int be[3], int bo[3]) {
+  int d2 = (d + 2) % 3;
+  face_extents(P, d, be);
+  for (int a = 0; a < 3; ++a) bo[a] = 0;
+  if (P.bc[d2] == HGKS_BC_ISOTHERMAL_WALL) {
+    be[d2] += 4;
+    bo[d2] = -2;
+  }
+}
+
+// One cell of the padded state, synthesised from the interior: periodic wrap,
+// or the isothermal-wall mirror (velocity reversed, same pressure,
+// temperature 2 T_w - T (not below 0.1 T_w), density p/T), all in FP64.
+__device__ __forceinline__ void load_cell(const double* __restrict__ q, const Params& P, int c0, int c1, int c2,
+                                          double v[5]) {
+  int c[3] = {c0, c1, c2};
+  bool mirror = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int N = P.n[a];
+    if (c[a] < 0 || c[a] >= N) {
+      if (P.bc[a] == HGKS_BC_ISOTHERMAL_WALL) {
+        mirror = true;
+        c[a] = c[a] < 0 ? -c[a] - 1 : 2 * N - 1 - c[a];
+      } else {
+        c[a] = ((c[a] % N) + N) % N;
+      }
+    }
+  }
+  const size_t n3 = cells(P);
+  const size_t idx = ((size_t)c[2] * P.n[1] + c[1]) * P.n[0] + c[0];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = q[k * n3 + idx];
+  if (mirror) {
+    double rho = v[0], ir = 1.0 / rho;
+    double U = v[1] * ir, V = v[2] * ir, W = v[3] * ir;
+    double p = P.gm1 * (v[4] - 0.5 * rho * (U * U + V * V + W * W));
+    double Tg = fmax(2.0 * P.T_wall - p * ir, 0.1 * P.T_wall);
+    double rg = p / Tg;
+    v[0] = rg;
+    v[1] = -rg * U;
+    v[2] = -rg * V;
+    v[3] = -rg * W;
+    v[4] = p / P.gm1 + 0.5 * rg * (U * U + V * V + W * W);
+  }
+}
+
+template <int DIR> struct ReconTile;  // faces per tile in the local frame (n, t1, t2)
+template <> struct ReconTile<0> { static constexpr int TN = 16, T1 = 4, T2 = 1; };
+template <> struct ReconTile<1> { static constexpr int TN = 1, T1 = 4, T2 = 16; };
+template <> struct ReconTile<2> { static constexpr int TN = 1, T1 = 16, T2 = 4; };
+
+template <int DIR> __host__ __device__ inline void recon_tile_extents(int S[3]) {
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  S[DIR] = ReconTile<DIR>::TN;
+  S[D1] = ReconTile<DIR>::T1;
+  S[D2] = ReconTile<DIR>::T2;
+}
+
+constexpr int RECON_THREADS = 128;
+
+// Normal sweep and first tangential sweep for a tile of faces of direction DIR.
+// LDS holds the 25 normal-sweep quantities of the tile plus a 2-face halo along
+// t1.  Output B[(q * 2 + g1) * NB + face] in the arithmetic type R.
+template <int DIR, class R>
+__global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __restrict__ q, Params P,
+                                                              const double* __restrict__ qref,
+                                                              R* __restrict__ B) {
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  constexpr int NA = ReconTile<DIR>::TN * (ReconTile<DIR>::T1 + 4) * ReconTile<DIR>::T2;
+  __shared__ R A[25][NA];
+
+  int S[3];
+  recon_tile_extents<DIR>(S);
+  int SA[3] = {S[0], S[1], S[2]};
+  SA[D1] += 4;
+  int be[3], bo[3];
+  b_extents(P, DIR, be, bo);
+  const int nt0 = (be[0] + S[0] - 1) / S[0], nt1 = (be[1] + S[1] - 1) / S[1];
+  const int bid = blockIdx.x;
+  int org[3];
+  org[0] = (bid % nt0) * S[0] + bo[0];
+  org[1] = ((bid / nt0) % nt1) * S[1] + bo[1];
+  org[2] = (bid / (nt0 * nt1)) * S[2] + bo[2];
+
+  // reference state subtracted before the reconstruction (zero on the FP64 path)
+  double ref[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) ref[k] = qref[k];
+  double rl[5];
+  rl[0] = ref[0];
+  rl[1] = ref[1 + DIR];
+  rl[2] = ref[1 + D1];
+  rl[3] = ref[1 + D2];
+  rl[4] = ref[4];
+
+  // ---- normal sweep on the tile and its t1 halo -------------------------
+  for (int idx = threadIdx.x; idx < NA; idx += RECON_THREADS) {
+    int l[3];
+    l[0] = idx % SA[0];
+    l[1] = (idx / SA[0]) % SA[1];
+    l[2] = idx / (SA[0] * SA[1]);
+    int f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] = org[a] + l[a] - (a == D1 ? 2 : 0);
+    bool ok = f[DIR] <= P.n[DIR] && f[D2] < bo[D2] + be[D2] && f[D1] >= -2 && f[D1] < P.n[D1] + 2;
+    if (!ok) continue;
+    R c[6][5];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      int cc[3] = {f[0], f[1], f[2]};
+      cc[DIR] += m - 3;
+      double v[5];
+      load_cell(q, P, cc[0], cc[1], cc[2], v);
+      c[m][0] = R(v[0] - rl[0]);
+      c[m][1] = R(v[1 + DIR] - rl[1]);
+      c[m][2] = R(v[1 + D1] - rl[2]);
+      c[m][3] = R(v[1 + D2] - rl[3]);
+      c[m][4] = R(v[4] - rl[4]);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R cv[6] = {c[0][k], c[1][k], c[2][k], c[3][k], c[4][k], c[5][k]};
+      R ql, qr, dl, dr, d0;
+      normal_sweep(cv, ql, qr, dl, dr, d0);
+      A[0 + k][idx] = ql;
+      A[5 + k][idx] = qr;
+      A[10 + k][idx] = dl;
+      A[15 + k][idx] = dr;
+      A[20 + k][idx] = d0;
+    }
+  }
+  __syncthreads();
+
+  // ---- first tangential sweep: one (face, Gauss line) per thread --------
+  const int o = threadIdx.x & 63, g1 = threadIdx.x >> 6;
+  int lo[3];
+  lo[0] = o % S[0];
+  lo[1] = (o / S[0]) % S[1];
+  lo[2] = o / (S[0] * S[1]);
+  int f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f[a] = org[a] + lo[a];
+  if (f[DIR] > P.n[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;
+  int ai[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    int l[3] = {lo[0], lo[1], lo[2]};
+    l[D1] += j;  // A tile is offset by -2 along t1
+    ai[j] = (l[2] * SA[1] + l[1]) * SA[0] + l[0];
+  }
+  const size_t NB = (size_t)be[0] * be[1] * be[2];
+  const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * be[0] + (f[0] - bo[0]);
+  R* out = B + (size_t)g1 * NB + bidx;
+  const size_t qstride = 2 * NB;
+  GaussPoint<R> gp(g1);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R v[5], val, der;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[0 + k][ai[j]];
+    gauss_value_slope(v, gp, val, der);
+    out[(B_QL + k) * qstride] = val;
+    out[(B_DLT1 + k) * qstride] = der;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[5 + k][ai[j]];
+    gauss_value_slope(v, gp, val, der);
+    out[(B_QR + k) * qstride] = val;
+    out[(B_DRT1 + k) * qstride] = der;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[10 + k][ai[j]];
+    out[(B_DLN + k) * qstride] = gauss_value(v, gp);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[15 + k][ai[j]];
+    out[(B_DRN + k) * qstride] = gauss_value(v, gp);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[20 + k][ai[j]];
+    out[(B_D0 + k) * qstride] = gauss_linear(v, gp);
+  }
+}
+
+constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
+
+// Second tangential sweep, Gauss-point flux, Gauss sum, F^n and dF^n/dt.
+// Lane layout in a wavefront: lanes 16 g .. 16 g + 15 hold Gauss point g of
+// 16 consecutive faces along x; the four waves of the block take four rows.
+template <int DIR, class R>
+__global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict__ B, Params P,
+                                                            const double* __restrict__ qref,
+                                                            const Scalars* __restrict__ sc, int use_residual_dt,
+                                                            double* __restrict__ F) {
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  int fe[3], be[3], bo[3];
+  face_extents(P, DIR, fe);
+  b_extents(P, DIR, be, bo);
+  const int nt0 = (fe[0] + 15) / 16, nt1 = (fe[1] + 3) / 4;
+  const int bid = blockIdx.x;
+  const int tid = threadIdx.x;
+  int f[3];
+  f[0] = (bid % nt0) * 16 + (tid & 15);
+  f[1] = ((bid / nt0) % nt1) * 4 + (tid >> 6);
+  f[2] = bid / (nt0 * nt1);
+  const int gpi = (tid >> 4) & 3;
+  const int g1 = gpi >> 1, g2 = gpi & 1;
+  const bool valid = f[0] < fe[0] && f[1] < fe[1] && f[2] < fe[2];
+  if (!valid) {  // keep the lane for the shuffles, on a valid face
+    f[0] = min(f[0], fe[0] - 1);
+    f[1] = min(f[1], fe[1] - 1);
+  }
+  const double dt = use_residual_dt ? sc->dt_residual : sc->dt;
+
+  // ---- second tangential sweep along t2 ----------------------------------
+  const size_t NB = (size_t)be[0] * be[1] * be[2];
+  const size_t qstride = 2 * NB;
+  size_t bi[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    int b[3] = {f[0], f[1], f[2]};
+    int t = f[D2] + j - 2;
+    if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
+    b[D2] = t;
+    bi[j] = (size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0]);
+  }
+  GaussPoint<R> gp(g2);
+  R ql[5], qr[5], dql[3][5], dqr[3][5], dq0n[5];
+  const R sn = R(P.dface[DIR][f[DIR]]);
+  const R st1 = R(P.dgp[D1][2 * f[D1] + g1]);
+  const R st2 = R(P.dgp[D2][2 * f[D2] + g2]);
+  double rl[5];
+  rl[0] = qref[0];
+  rl[1] = qref[1 + DIR];
+  rl[2] = qref[1 + D1];
+  rl[3] = qref[1 + D2];
+  rl[4] = qref[4];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R v[5], val, der;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_QL + k) * qstride + bi[j]];
+    gauss_value_slope(v, gp, val, der);
+    ql[k] = R(double(val) + rl[k]);
+    dql[2][k] = der * st2;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_QR + k) * qstride + bi[j]];
+    gauss_value_slope(v, gp, val, der);
+    qr[k] = R(double(val) + rl[k]);
+    dqr[2][k] = der * st2;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_DLN + k) * qstride + bi[j]];
+    dql[0][k] = gauss_value(v, gp) * sn;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_DRN + k) * qstride + bi[j]];
+    dqr[0][k] = gauss_value(v, gp) * sn;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_DLT1 + k) * qstride + bi[j]];
+    dql[1][k] = gauss_value(v, gp) * st1;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_DRT1 + k) * qstride + bi[j]];
+    dqr[1][k] = gauss_value(v, gp) * st1;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[(B_D0 + k) * qstride + bi[j]];
+    dq0n[k] = gauss_linear(v, gp) * sn;
+  }
+
+  // ---- kinetic flux at the Gauss point -----------------------------------
+  GasParams<R> g;
+  g.gm1 = R(P.gm1);
+  g.K = R(P.K);
+  g.mu_ref = R(P.mu_ref);
+  g.T_ref = R(P.T_ref);
+  g.mu_exp = R(P.mu_exp);
+  g.pr_fix = R(P.pr_fix);
+  R F1[5], F2[5];
+  gp_flux(ql, qr, dql, dqr, dq0n, g, R(dt), F1, F2);
+
+  // ---- 2x2 Gauss sum across the four lanes of the face -------------------
+  double s1[5], s2[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    s1[k] = double(F1[k]);
+    s2[k] = double(F2[k]);
+    s1[k] += __shfl_xor(s1[k], 16);
+    s2[k] += __shfl_xor(s2[k], 16);
+    s1[k] += __shfl_xor(s1[k], 32);
+    s2[k] += __shfl_xor(s2[k], 32);
+  }
+  if (!valid || gpi != 0) return;
+  const double area = P.hcell[D1][f[D1]] * P.hcell[D2][f[D2]];
+  double loc[10];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double I1 = 0.25 * area * s1[k];  // integral over [0, dt]
+    double I2 = 0.25 * area * s2[k];  // integral over [0, dt/2]
+    loc[k] = (4.0 * I2 - I1) / dt;
+    loc[5 + k] = 4.0 * (I1 - 2.0 * I2) / (dt * dt);
+  }
+  const size_t NF = (size_t)fe[0] * fe[1] * fe[2];
+  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fe[0] + f[0];
+  // rotate momentum back to the global frame
+  const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F[gcomp[k] * NF + fi] = loc[k];
+    F[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
+  }
+}
+
+// L and dL/dt of one cell from the six face fluxes, plus the body-force source
+// S = (0, rho f, m . f) and its time derivative (0, f L_rho, f . L_m).
+__device__ __forceinline__ void cell_residual(const double* __restrict__ qe, const double* __restrict__ F0,
+                                              const double* __restrict__ F1, const double* __restrict__ F2,
+                                              const Params& P, int i, int j, int k, double L[5], double dL[5]) {
+  const size_t n3 = cells(P);
+  const size_t c = ((size_t)k * P.n[1] + j) * P.n[0] + i;
+  const double vol = P.hcell[0][i] * P.hcell[1][j] * P.hcell[2][k];
+  const double* Fd[3] = {F0, F1, F2};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) { L[m] = 0.0; dL[m] = 0.0; }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int fe[3];
+    face_extents(P, d, fe);
+    const size_t NF = (size_t)fe[0] * fe[1] * fe[2];
+    const size_t fm = ((size_t)k * fe[1] + j) * fe[0] + i;
+    const size_t step = d == 0 ? 1 : (d == 1 ? (size_t)fe[0] : (size_t)fe[0] * fe[1]);
+    const size_t fp = fm + step;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      L[m] -= (Fd[d][m * NF + fp] - Fd[d][m * NF + fm]) / vol;
+      dL[m] -= (Fd[d][(5 + m) * NF + fp] - Fd[d][(5 + m) * NF + fm]) / vol;
+    }
+  }
+  const double rho = qe[c], mx = qe[n3 + c], my = qe[2 * n3 + c], mz = qe[3 * n3 + c];
+  const double lrho = L[0];
+  L[1] += rho * P.force[0];
+  L[2] += rho * P.force[1];
+  L[3] += rho * P.force[2];
+  L[4] += mx * P.force[0] + my * P.force[1] + mz * P.force[2];
+  dL[1] += P.force[0] * lrho;
+  dL[2] += P.force[1] * lrho;
+  dL[3] += P.force[2] * lrho;
+  dL[4] += P.force[0] * L[1] + P.force[1] * L[2] + P.force[2] * L[3];
+}
+
+// Wave speed max_d (|U_d| + c) / h_d of one cell.
+__device__ __forceinline__ double cell_wave_rate(const double v[5], const Params& P, int i, int j, int k) {
+  double ir = 1.0 / v[0];
+  double U = v[1] * ir, V = v[2] * ir, W = v[3] * ir;
+  double p = P.gm1 * (v[4] - 0.5 * v[0] * (U * U + V * V + W * W));
+  double c = sqrt(P.gamma * p * ir);
+  double r = (fabs(U) + c) / P.hcell[0][i];
+  r = fmax(r, (fabs(V) + c) / P.hcell[1][j]);
+  r = fmax(r, (fabs(W) + c) / P.hcell[2][k]);
+  return r;
+}
+
+// Block max of a non-negative double, then one atomic max on its bit pattern
+// (non-negative doubles order like their unsigned 64-bit patterns).
+__device__ __forceinline__ void block_max_atomic(double r, unsigned long long* dst) {
+  __shared__ double red[16];
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+constexpr int CELL_THREADS = 256;
+
+template <int STAGE>
+__global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict__ q, double* __restrict__ qs,
+                                                              double* __restrict__ acc, const double* __restrict__ F0,
+                                                              const double* __restrict__ F1,
+                                                              const double* __restrict__ F2, Params P,
+                                                              Scalars* __restrict__ sc) {
+  const size_t n3 = cells(P);
+  const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  double rate = 0.0;
+  if (c < n3) {
+    const int i = (int)(c % P.n[0]);
+    const int j = (int)((c / P.n[0]) % P.n[1]);
+    const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
+    const double dt = sc->dt;
+    double L[5], dL[5];
+    if (STAGE == 1) {
+      cell_residual(q, F0, F1, F2, P, i, j, k, L, dL);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double qn = q[m * n3 + c];
+        qs[m * n3 + c] = qn + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m];
+        acc[m * n3 + c] = qn + dt * L[m] + dt * dt / 6.0 * dL[m];
+      }
+    } else {
+      cell_residual(qs, F0, F1, F2, P, i, j, k, L, dL);
+      double v[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        v[m] = acc[m * n3 + c] + dt * dt / 3.0 * dL[m];
+        q[m * n3 + c] = v[m];
+      }
+      rate = cell_wave_rate(v, P, i, j, k);
+    }
+  }
+  if (STAGE == 2) block_max_atomic(rate, &sc->smax);
+}
+
+__global__ __launch_bounds__(CELL_THREADS) void residual_kernel(const double* __restrict__ qe,
+                                                                const double* __restrict__ F0,
+                                                                const double* __restrict__ F1,
+                                                                const double* __restrict__ F2, Params P,
+                                                                double* __restrict__ Lo, double* __restrict__ dLo) {
+  const size_t n3 = cells(P);
+  const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  if (c >= n3) return;
+  const int i = (int)(c % P.n[0]);
+  const int j = (int)((c / P.n[0]) % P.n[1]);
+  const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
+  double L[5], dL[5];
+  cell_residual(qe, F0, F1, F2, P, i, j, k, L, dL);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    Lo[m * n3 + c] = L[m];
+    dLo[m * n3 + c] = dL[m];
+  }
+}
+
+__global__ __launch_bounds__(CELL_THREADS) void wave_rate_kernel(const double* __restrict__ q, Params P,
+                                                                 Scalars* __restrict__ sc) {
+  const size_t n3 = cells(P);
+  const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  double rate = 0.0;
+  if (c < n3) {
+    const int i = (int)(c % P.n[0]);
+    const int j = (int)((c / P.n[0]) % P.n[1]);
+    const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
+    double v[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) v[m] = q[m * n3 + c];
+    rate = cell_wave_rate(v, P, i, j, k);
+  }
+  block_max_atomic(rate, &sc->smax);
+}
+
+// Start of a step: choose dt (fixed, or CFL from the wave-speed maximum of
+// the current state), advance the clock, clear the maximum for stage 2.
+__global__ void begin_step_kernel(Scalars* sc, double cfl, double dt_fixed) {
+  if (threadIdx.x != 0) return;
+  const double smax = __longlong_as_double((long long)sc->smax);
+  const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / smax;
+  sc->dt = dt;
+  sc->t += dt;
+  sc->steps += 1.0;
+  sc->smax = 0ull;
+}
+
+__global__ void set_scalar_kernel(double* dst, double v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+
+// ---- statistics ----------------------------------------------------------
+enum { ST_EK = 0, ST_ENS, ST_DIL, ST_TOT, ST_MAX = ST_TOT + 5, ST_MINP = ST_MAX + 5, ST_MINR, ST_BAD, ST_COUNT };
+
+__device__ __forceinline__ double vel(const double* __restrict__ q, const Params& P, int comp, int i, int j, int k) {
+  double v[5];
+  load_cell(q, P, i, j, k, v);
+  return v[1 + comp] / v[0];
+}
+
+// Fourth-order central difference of U_comp along axis, in index space
+// scaled by d(index)/dx at the cell centre.
+__device__ __forceinline__ double dvel(const double* __restrict__ q, const Params& P, int comp, int axis, int i,
+                                       int j, int k) {
+  int o[3] = {0, 0, 0};
+  o[axis] = 1;
+  double m2 = vel(q, P, comp, i - 2 * o[0], j - 2 * o[1], k - 2 * o[2]);
+  double m1 = vel(q, P, comp, i - o[0], j - o[1], k - o[2]);
+  double p1 = vel(q, P, comp, i + o[0], j + o[1], k + o[2]);
+  double p2 = vel(q, P, comp, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2]);
+  int ia = axis == 0 ? i : (axis == 1 ? j : k);
+  return (m2 - 8.0 * m1 + 8.0 * p1 - p2) / 12.0 * P.dcen[axis][ia];
+}
+
+__global__ __launch_bounds__(CELL_THREADS) void stats_partial_kernel(const double* __restrict__ q, Params P,
+                                                                     double* __restrict__ part) {
+  __shared__ double red[ST_COUNT][CELL_THREADS];
+  const size_t n3 = cells(P);
+  const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  double s[ST_COUNT];
+  for (int m = 0; m < ST_COUNT; ++m) s[m] = 0.0;
+  s[ST_MINP] = INFINITY;
+  s[ST_MINR] = INFINITY;
+  if (c < n3) {
+    const int i = (int)(c % P.n[0]);
+    const int j = (int)((c / P.n[0]) % P.n[1]);
+    const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
+    double v[5];
+    for (int m = 0; m < 5; ++m) v[m] = q[m * n3 + c];
+    const double dv = P.hcell[0][i] * P.hcell[1][j] * P.hcell[2][k];
+    const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0];
+    const double p = P.gm1 * (v[4] - ke);
+    s[ST_EK] = ke * dv;
+    double gr[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) gr[a][b] = dvel(q, P, a, b, i, j, k);
+    const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
+    const double dv_ = gr[0][0] + gr[1][1] + gr[2][2];
+    s[ST_ENS] = (wx * wx + wy * wy + wz * wz) * dv;
+    s[ST_DIL] = dv_ * dv_ * dv;
+    bool bad = false;
+    for (int m = 0; m < 5; ++m) {
+      s[ST_TOT + m] = v[m] * dv;
+      s[ST_MAX + m] = fabs(v[m]);
+      bad = bad || !isfinite(v[m]);
+    }
+    s[ST_MINP] = p;
+    s[ST_MINR] = v[0];
+    s[ST_BAD] = bad ? 1.0 : 0.0;
+  }
+  for (int m = 0; m < ST_COUNT; ++m) red[m][threadIdx.x] = s[m];
+  __syncthreads();
+  for (int w = CELL_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int m = 0; m < ST_COUNT; ++m) {
+        double a = red[m][threadIdx.x], b = red[m][threadIdx.x + w];
+        if (m >= ST_MAX && m < ST_MAX + 5) red[m][threadIdx.x] = fmax(a, b);
+        else if (m == ST_MINP || m == ST_MINR) red[m][threadIdx.x] = fmin(a, b);
+        else if (m == ST_BAD) red[m][threadIdx.x] = fmax(a, b);
+        else red[m][threadIdx.x] = a + b;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < ST_COUNT) part[(size_t)blockIdx.x * ST_COUNT + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Deterministic final reduction: thread m reduces field m over all blocks in order.
+__global__ void stats_final_kernel(const double* __restrict__ part, int nblocks, double* __restrict__ out) {
+  const int m = threadIdx.x;
+  if (m >= ST_COUNT) return;
+  double a = part[m];
+  for (int b = 1; b < nblocks; ++b) {
+    double x = part[(size_t)b * ST_COUNT + m];
+    if (m >= ST_MAX && m < ST_MAX + 5) a = fmax(a, x);
+    else if (m == ST_MINP || m == ST_MINR) a = fmin(a, x);
+    else if (m == ST_BAD) a = fmax(a, x);
+    else a += x;
+  }
+  out[m] = a;
+}
+
+}  // namespace hgks
+
+// ===========================================================================
+// Host side: context, workspace layout, launches, C ABI.
+// ===========================================================================
+using namespace hgks;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t qs, acc, B, F[3], metric[3][4], scal, part, qref, total;
+  size_t nb_elems;  // elements of B (per direction maximum)
+  int stat_blocks;
+};
+
+bool precision_mixed(const hgks_config& c) { return c.precision == HGKS_MIXED; }
+
+Layout make_layout(const hgks_config& c) {
+  Params P{};
+  for (int a = 0; a < 3; ++a) { P.n[a] = c.n[a]; P.bc[a] = c.bc[a]; }
+  Layout L{};
+  size_t off = 0;
+  const size_t n3 = (size_t)c.n[0] * c.n[1] * c.n[2];
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.qs = take(5 * n3 * sizeof(double));
+  L.acc = take(5 * n3 * sizeof(double));
+  size_t nb = 0;
+  for (int d = 0; d < 3; ++d) {
+    int be[3], bo[3];
+    b_extents(P, d, be, bo);
+    nb = std::max(nb, (size_t)be[0] * be[1] * be[2]);
+  }
+  L.nb_elems = (size_t)B_COUNT * 2 * nb;
+  L.B = take(L.nb_elems * (precision_mixed(c) ? sizeof(float) : sizeof(double)));
+  for (int d = 0; d < 3; ++d) {
+    int fe[3];
+    face_extents(P, d, fe);
+    L.F[d] = take((size_t)10 * fe[0] * fe[1] * fe[2] * sizeof(double));
+  }
+  for (int a = 0; a < 3; ++a) {
+    L.metric[a][0] = take(c.n[a] * sizeof(double));            // hcell
+    L.metric[a][1] = take((c.n[a] + 1) * sizeof(double));      // dface
+    L.metric[a][2] = take(2 * c.n[a] * sizeof(double));        // dgp
+    L.metric[a][3] = take(c.n[a] * sizeof(double));            // dcen
+  }
+  L.scal = take(sizeof(Scalars));
+  L.stat_blocks = (int)((n3 + CELL_THREADS - 1) / CELL_THREADS);
+  L.part = take(((size_t)L.stat_blocks + 1) * ST_COUNT * sizeof(double));
+  L.qref = take(5 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// Coordinate map of axis a: x(xi), xi in [0, n] the continuous cell index.
+// Uniform, or (axis 1 with y_stretch = b > 0) the tanh map of Sec. 4.2:
+// x = lo + (hi - lo) (1 + tanh(b (2 xi/n - 1)) / tanh b) / 2.
+double coord(const hgks_config& c, int a, double xi) {
+  const double Lh = c.hi[a] - c.lo[a];
+  if (a == 1 && c.y_stretch > 0.0) {
+    const double b = c.y_stretch;
+    return c.lo[a] + 0.5 * Lh * (1.0 + std::tanh(b * (2.0 * xi / c.n[a] - 1.0)) / std::tanh(b));
+  }
+  return c.lo[a] + Lh * xi / c.n[a];
+}
+double dcoord(const hgks_config& c, int a, double xi) {
+  const double Lh = c.hi[a] - c.lo[a];
+  if (a == 1 && c.y_stretch > 0.0) {
+    const double b = c.y_stretch;
+    const double ch = std::cosh(b * (2.0 * xi / c.n[a] - 1.0));
+    return Lh * b / (c.n[a] * std::tanh(b) * ch * ch);
+  }
+  return Lh / c.n[a];
+}
+
+const char* kStatus[] = {"ok", "invalid argument", "out of memory", "device error", "non-finite state",
+                         "non-positive density or pressure", "unsupported"};
+
+}  // namespace
+
+struct hgks_ctx_s {
+  hgks_config cfg;
+  hipStream_t stream;
+  double* q;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  Params P;
+  double* qs;
+  double* acc;
+  void* B;
+  double* F[3];
+  Scalars* sc;
+  double* part;
+  double* qref;
+  hgks_status latched;
+  double t0;
+  std::string err;
+  // profiling: event pairs per launch, in launch order
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_class;
+  size_t ev_used = 0;
+};
+
+enum { PROF_RECON = 0, PROF_FLUX = 1, PROF_UPDATE = 2, PROF_OTHER = 3 };
+
+// Record the start event of a launch of class cls (no-op unless profiling).
+static hipError_t prof_begin(hgks_ctx ctx, int cls) {
+  if (!ctx->prof) return hipSuccess;
+  if (ctx->ev_used + 2 > ctx->ev_pool.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ctx->ev_pool.push_back(e);
+    }
+  }
+  if (ctx->ev_class.size() < ctx->ev_pool.size() / 2) ctx->ev_class.resize(ctx->ev_pool.size() / 2);
+  ctx->ev_class[ctx->ev_used / 2] = cls;
+  return hipEventRecord(ctx->ev_pool[ctx->ev_used], ctx->stream);
+}
+static hipError_t prof_end(hgks_ctx ctx) {
+  if (!ctx->prof) return hipSuccess;
+  hipError_t r = hipEventRecord(ctx->ev_pool[ctx->ev_used + 1], ctx->stream);
+  ctx->ev_used += 2;
+  return r;
+}
+
+static hgks_status validate(const hgks_config* c, std::string* why) {
+  auto bad = [&](const char* m) { if (why) *why = m; return HGKS_E_INVALID; };
+  if (!c) return bad("null config");
+  if (c->abi_version != HGKS_ABI_VERSION) return bad("abi_version mismatch");
+  for (int a = 0; a < 3; ++a) {
+    if (c->n[a] < 4) return bad("each n must be >= 4");
+    if (!(c->hi[a] > c->lo[a])) return bad("hi must exceed lo");
+    if (c->bc[a] != HGKS_BC_PERIODIC && c->bc[a] != HGKS_BC_ISOTHERMAL_WALL) return bad("unknown bc");
+    if (c->bc[a] == HGKS_BC_ISOTHERMAL_WALL && a != 1) return bad("walls are supported on the y axis only");
+  }
+  if ((size_t)c->n[0] * c->n[1] * c->n[2] > ((size_t)1 << 34)) return bad("grid too large");
+  if (!(c->gamma > 1.0 && c->gamma <= 5.0 / 3.0)) return bad("gamma out of (1, 5/3]");
+  if (!(c->prandtl > 0.0)) return bad("prandtl must be > 0");
+  if (!(c->mu_ref >= 0.0)) return bad("mu_ref must be >= 0");
+  if (c->mu_exp != 0.0 && !(c->T_ref > 0.0)) return bad("T_ref must be > 0 with a power-law viscosity");
+  if (c->bc[1] == HGKS_BC_ISOTHERMAL_WALL && !(c->T_wall > 0.0)) return bad("T_wall must be > 0");
+  if (!(c->y_stretch >= 0.0)) return bad("y_stretch must be >= 0");
+  if (!(c->cfl > 0.0)) return bad("cfl must be > 0");
+  if (!(c->rho_ref > 0.0)) return bad("rho_ref must be > 0");
+  if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return bad("unknown precision");
+  if (c->flags != 0) return bad("flags must be 0");
+  return HGKS_OK;
+}
+
+#define HIP_TRY(ctx, expr)                                                               \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
+      return HGKS_E_DEVICE;                                                              \
+    }                                                                                    \
+  } while (0)
+
+template <class R>
+static hgks_status launch_fluxes(hgks_ctx ctx, const double* qin, int use_residual_dt) {
+  const Params& P = ctx->P;
+  R* B = static_cast<R*>(ctx->B);
+  const double* qref = ctx->qref;
+  auto recon_blocks = [&](int d, int S0, int S1, int S2) {
+    int be[3], bo[3];
+    b_extents(P, d, be, bo);
+    return (unsigned)(((be[0] + S0 - 1) / S0) * ((be[1] + S1 - 1) / S1) * ((be[2] + S2 - 1) / S2));
+  };
+  auto flux_blocks = [&](int d) {
+    int fe[3];
+    face_extents(P, d, fe);
+    return (unsigned)(((fe[0] + 15) / 16) * ((fe[1] + 3) / 4) * fe[2]);
+  };
+  int S[3];
+#define HGKS_DIRECTION(D)                                                                                    \
+  recon_tile_extents<D>(S);                                                                                  \
+  HIP_TRY(ctx, prof_begin(ctx, PROF_RECON));                                                                 \
+  hipLaunchKernelGGL((recon_kernel<D, R>), dim3(recon_blocks(D, S[0], S[1], S[2])), dim3(RECON_THREADS), 0,  \
+                     ctx->stream, qin, P, qref, B);                                                          \
+  HIP_TRY(ctx, prof_end(ctx));                                                                               \
+  HIP_TRY(ctx, prof_begin(ctx, PROF_FLUX));                                                                  \
+  hipLaunchKernelGGL((flux_kernel<D, R>), dim3(flux_blocks(D)), dim3(FLUX_THREADS), 0, ctx->stream, B, P,   \
+                     qref, ctx->sc, use_residual_dt, ctx->F[D]);                                             \
+  HIP_TRY(ctx, prof_end(ctx));
+  HGKS_DIRECTION(0)
+  HGKS_DIRECTION(1)
+  HGKS_DIRECTION(2)
+#undef HGKS_DIRECTION
+  HIP_TRY(ctx, hipGetLastError());
+  return HGKS_OK;
+}
+
+static hgks_status launch_fluxes_any(hgks_ctx ctx, const double* qin, int use_residual_dt) {
+  if (precision_mixed(ctx->cfg)) return launch_fluxes<float>(ctx, qin, use_residual_dt);
+  return launch_fluxes<double>(ctx, qin, use_residual_dt);
+}
+
+static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CELL_THREADS - 1) / CELL_THREADS); }
+
+extern "C" {
+
+hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes) {
+  if (!bytes) return HGKS_E_INVALID;
+  hgks_status s = validate(cfg, nullptr);
+  if (s != HGKS_OK) return s;
+  *bytes = make_layout(*cfg).total;
+  return HGKS_OK;
+}
+
+hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_t ws_bytes, void* hip_stream,
+                      double t0, hgks_ctx* out) {
+  if (!out) return HGKS_E_INVALID;
+  *out = nullptr;
+  hgks_status s = validate(cfg, nullptr);
+  if (s != HGKS_OK) return s;
+  if (!q_dev || !ws_dev) return HGKS_E_INVALID;
+  if (((uintptr_t)ws_dev & 255u) != 0 || ((uintptr_t)q_dev & 7u) != 0) return HGKS_E_INVALID;
+  Layout L = make_layout(*cfg);
+  if (ws_bytes < L.total) return HGKS_E_INVALID;
+  hgks_ctx ctx = new (std::nothrow) hgks_ctx_s();
+  if (!ctx) return HGKS_E_NOMEM;
+  ctx->cfg = *cfg;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->q = q_dev;
+  ctx->ws = static_cast<char*>(ws_dev);
+  ctx->ws_bytes = ws_bytes;
+  ctx->L = L;
+  ctx->latched = HGKS_OK;
+  ctx->t0 = t0;
+  Params& P = ctx->P;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = cfg->n[a];
+    P.bc[a] = cfg->bc[a];
+    P.force[a] = cfg->body_force[a];
+  }
+  P.gamma = cfg->gamma;
+  P.gm1 = cfg->gamma - 1.0;
+  P.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
+  P.mu_ref = cfg->mu_ref;
+  P.T_ref = cfg->T_ref;
+  P.mu_exp = cfg->mu_exp;
+  P.pr_fix = 1.0 / cfg->prandtl - 1.0;
+  P.T_wall = cfg->T_wall;
+  ctx->qs = reinterpret_cast<double*>(ctx->ws + L.qs);
+  ctx->acc = reinterpret_cast<double*>(ctx->ws + L.acc);
+  ctx->B = ctx->ws + L.B;
+  for (int d = 0; d < 3; ++d) ctx->F[d] = reinterpret_cast<double*>(ctx->ws + L.F[d]);
+  ctx->sc = reinterpret_cast<Scalars*>(ctx->ws + L.scal);
+  ctx->part = reinterpret_cast<double*>(ctx->ws + L.part);
+  ctx->qref = reinterpret_cast<double*>(ctx->ws + L.qref);
+
+  // geometry: widths, d(index)/dx at faces, Gauss points and centres
+  std::vector<double> host;
+  std::vector<size_t> where;
+  const double r3 = std::sqrt(3.0) / 6.0;
+  for (int a = 0; a < 3; ++a) {
+    const int n = cfg->n[a];
+    const bool stretched = a == 1 && cfg->y_stretch > 0.0;
+    const double hu = (cfg->hi[a] - cfg->lo[a]) / n;
+    std::vector<double> h(n), df(n + 1), dg(2 * n), dc(n);
+    for (int i = 0; i < n; ++i) {
+      h[i] = stretched ? coord(*cfg, a, i + 1.0) - coord(*cfg, a, double(i)) : hu;
+      dg[2 * i] = stretched ? 1.0 / dcoord(*cfg, a, i + 0.5 - r3) : 1.0 / hu;
+      dg[2 * i + 1] = stretched ? 1.0 / dcoord(*cfg, a, i + 0.5 + r3) : 1.0 / hu;
+      dc[i] = stretched ? 1.0 / dcoord(*cfg, a, i + 0.5) : 1.0 / hu;
+    }
+    for (int f = 0; f <= n; ++f) df[f] = stretched ? 1.0 / dcoord(*cfg, a, double(f)) : 1.0 / hu;
+    const std::vector<double>* arr[4] = {&h, &df, &dg, &dc};
+    for (int m = 0; m < 4; ++m) {
+      double* dst = reinterpret_cast<double*>(ctx->ws + L.metric[a][m]);
+      HIP_TRY(ctx, hipMemcpyAsync(dst, arr[m]->data(), arr[m]->size() * sizeof(double), hipMemcpyHostToDevice,
+                                  ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    P.hcell[a] = reinterpret_cast<const double*>(ctx->ws + L.metric[a][0]);
+    P.dface[a] = reinterpret_cast<const double*>(ctx->ws + L.metric[a][1]);
+    P.dgp[a] = reinterpret_cast<const double*>(ctx->ws + L.metric[a][2]);
+    P.dcen[a] = reinterpret_cast<const double*>(ctx->ws + L.metric[a][3]);
+  }
+  Scalars s0{};
+  s0.t = t0;
+  double qref[5] = {0, 0, 0, 0, 0};
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->sc, &s0, sizeof(Scalars), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->qref, qref, sizeof(qref), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  hipLaunchKernelGGL(wave_rate_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->sc);
+  HIP_TRY(ctx, hipGetLastError());
+  *out = ctx;
+  return HGKS_OK;
+}
+
+hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
+  if (!ctx || nsteps < 0 || !std::isfinite(dt_fixed)) return HGKS_E_INVALID;
+  if (ctx->latched != HGKS_OK) return ctx->latched;
+  const Params& P = ctx->P;
+  for (int s = 0; s < nsteps; ++s) {
+    HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
+    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->sc, ctx->cfg.cfl, dt_fixed);
+    HIP_TRY(ctx, prof_end(ctx));
+    hgks_status r = launch_fluxes_any(ctx, ctx->q, 0);
+    if (r != HGKS_OK) return r;
+    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
+    hipLaunchKernelGGL(update_kernel<1>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
+                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc);
+    HIP_TRY(ctx, prof_end(ctx));
+    r = launch_fluxes_any(ctx, ctx->qs, 0);
+    if (r != HGKS_OK) return r;
+    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
+    hipLaunchKernelGGL(update_kernel<2>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
+                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc);
+    HIP_TRY(ctx, prof_end(ctx));
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out) {
+  if (!ctx || !out) return HGKS_E_INVALID;
+  const Params& P = ctx->P;
+  const int nb = ctx->L.stat_blocks;
+  double* fin = ctx->part + (size_t)nb * ST_COUNT;
+  hipLaunchKernelGGL(stats_partial_kernel, dim3(nb), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->part);
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->part, nb, fin);
+  HIP_TRY(ctx, hipGetLastError());
+  double h[ST_COUNT];
+  Scalars sc;
+  HIP_TRY(ctx, hipMemcpyAsync(h, fin, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(&sc, ctx->sc, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double vol = 1.0;
+  for (int a = 0; a < 3; ++a) vol *= ctx->cfg.hi[a] - ctx->cfg.lo[a];
+  const double rho0 = ctx->cfg.rho_ref, mu = ctx->cfg.mu_ref;
+  std::memset(out, 0, sizeof(*out));
+  out->t = sc.t;
+  out->dt_last = sc.dt;
+  out->steps = (int64_t)sc.steps;
+  out->Ek = h[ST_EK] / (rho0 * vol);
+  out->eps_sol = mu * h[ST_ENS] / (rho0 * vol);
+  out->eps_dil = 4.0 / 3.0 * mu * h[ST_DIL] / (rho0 * vol);
+  out->eps_com = out->eps_sol + out->eps_dil;
+  for (int m = 0; m < 5; ++m) {
+    out->total[m] = h[ST_TOT + m];
+    out->max_abs[m] = h[ST_MAX + m];
+  }
+  out->min_p = h[ST_MINP];
+  out->min_rho = h[ST_MINR];
+  out->nonfinite = h[ST_BAD] != 0.0 ? 1 : 0;
+  if (out->nonfinite) ctx->latched = HGKS_E_NONFINITE;
+  else if (!(out->min_p > 0.0) || !(out->min_rho > 0.0)) ctx->latched = HGKS_E_NEGATIVE_STATE;
+  return HGKS_OK;
+}
+
+hgks_status hgks_dt(hgks_ctx ctx, double* dt_out) {
+  if (!ctx || !dt_out) return HGKS_E_INVALID;
+  Scalars sc;
+  HIP_TRY(ctx, hipMemcpyAsync(&sc, ctx->sc, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const double smax = __builtin_bit_cast(double, sc.smax);
+  *dt_out = ctx->cfg.cfl / smax;
+  return HGKS_OK;
+}
+
+hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* L_dev, double* dL_dev) {
+  if (!ctx || !q_dev || !L_dev || !dL_dev || !(dt > 0.0)) return HGKS_E_INVALID;
+  const Params& P = ctx->P;
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, &ctx->sc->dt_residual, dt);
+  hgks_status r = launch_fluxes_any(ctx, q_dev, 1);
+  if (r != HGKS_OK) return r;
+  hipLaunchKernelGGL(residual_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, q_dev, ctx->F[0],
+                     ctx->F[1], ctx->F[2], P, L_dev, dL_dev);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return HGKS_OK;
+}
+
+hgks_status hgks_profile(hgks_ctx ctx, int32_t enable) {
+  if (!ctx) return HGKS_E_INVALID;
+  ctx->prof = enable != 0;
+  return HGKS_OK;
+}
+
+hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int64_t launches[HGKS_PROFILE_CLASSES]) {
+  if (!ctx || !ms || !launches) return HGKS_E_INVALID;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int c = 0; c < HGKS_PROFILE_CLASSES; ++c) { ms[c] = 0.0; launches[c] = 0; }
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float t = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
+    const int c = ctx->ev_class[i / 2];
+    ms[c] += t;
+    launches[c] += 1;
+  }
+  ctx->ev_used = 0;
+  return HGKS_OK;
+}
+
+hgks_status hgks_destroy(hgks_ctx ctx) {
+  if (!ctx) return HGKS_E_INVALID;
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return HGKS_OK;
+}
+
+const char* hgks_status_string(hgks_status s) {
+  int i = (int)s;
+  if (i < 0 || i > 6) return "unknown status";
+  return kStatus[i];
+}
+
+const char* hgks_last_error(hgks_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+that include/hgks.h declares, the ctypes structs match the C layout, and
+configuration validation rejects bad input (no device work involved)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2207_01173_amd import hgks
+from paper_2207_01173_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgks.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(hgks_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = hgks.lib()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hgks.EXPORTED)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "hgks.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(hgks_config),"
+        " offsetof(hgks_config, precision), offsetof(hgks_config, rho_ref), sizeof(hgks_stats_t),"
+        " offsetof(hgks_stats_t, nonfinite), offsetof(hgks_stats_t, total)); return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    ref = [ctypes.sizeof(hgks.hgks_config), hgks.hgks_config.precision.offset, hgks.hgks_config.rho_ref.offset,
+           ctypes.sizeof(hgks.hgks_stats_t), hgks.hgks_stats_t.nonfinite.offset, hgks.hgks_stats_t.total.offset]
+    assert got == ref
+
+
+def test_workspace_size_and_validation():
+    p = W.tgv_params(32)
+    cfg = hgks.make_config(p)
+    n = hgks.hgks_workspace_size(cfg)
+    # at least Q*, the accumulator and three face-flux buffers
+    assert n >= 2 * 5 * 32 ** 3 * 8 + 3 * 10 * 33 * 32 * 32 * 8
+    bad = [
+        ("abi_version", 99), ("precision", 7), ("flags", 1), ("gamma", 1.0), ("cfl", 0.0), ("prandtl", 0.0),
+        ("rho_ref", 0.0), ("mu_ref", -1.0),
+    ]
+    for field, val in bad:
+        c = hgks.make_config(p)
+        setattr(c, field, val)
+        with pytest.raises(hgks.HGKSError) as e:
+            hgks.hgks_workspace_size(c)
+        assert e.value.status == hgks.HGKS_E_INVALID, field
+    c = hgks.make_config(p)
+    c.n[1] = 3
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(c)
+    c = hgks.make_config(p)
+    c.bc[0] = hgks.BC_ISOTHERMAL_WALL  # walls only on y
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(c)
+    c = hgks.make_config(p)
+    c.hi[2] = c.lo[2]
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(c)
+
+
+def test_mixed_workspace_smaller():
+    p = W.tgv_params(32)
+    assert hgks.hgks_workspace_size(hgks.make_config(p, hgks.MIXED)) < hgks.hgks_workspace_size(hgks.make_config(p))
+
+
+def test_status_strings():
+    L = hgks.lib()
+    for s in range(7):
+        assert L.hgks_status_string(s)
+    assert L.hgks_status_string(42) == b"unknown status"

@@ -1,0 +1,224 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bar (FP64 path): the state after 10 S2O4 steps of the 32^3 TGV matches the
+oracle to 1e-11 in the relative max-norm per component; single residuals and
+statistics to 1e-12; uniform flow is preserved bitwise.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2207_01173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_01173_amd import hgks
+
+    hgks.lib()
+    return hgks
+
+
+def rel_err(got, ref):
+    """Per component: max |got - ref| / max |ref| (max-norm relative error)."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    axes = tuple(range(1, ref.ndim))
+    return np.abs(got - ref).max(axis=axes) / np.maximum(np.abs(ref).max(axis=axes), 1e-300)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n,seed", [((37, 21, 19), 3), ((4, 5, 6), 4), ((16, 16, 16), 5), ((33, 8, 12), 6)])
+def test_residual_parity(hg, oracle, n, seed):
+    """L(Q) and dL/dt on smooth random periodic data spanning several tiles
+    with ragged tails, and the minimum grid size."""
+    p = W.tgv_params(n, ma=0.3, re=300.0)
+    q = W.smooth_random(p, seed=seed)
+    dt = 0.01
+    say("residual parity", n, seed)
+    s = hg.Solver(p, q)
+    L, dL = s.residual(q, dt)
+    L, dL = L.cpu().numpy(), dL.cpu().numpy()
+    Lo, dLo = oracle.residual(p, q, dt)
+    eL, edL = rel_err(L, Lo), rel_err(dL, dLo)
+    say("  L err", eL, "dL err", edL)
+    assert (eL <= 1e-12).all() and (edL <= 1e-12).all()
+    s.close()
+
+
+def test_tgv32_ten_steps(hg, oracle):
+    """P16: TGV 32^3 (Ma 0.1, Re 1600, Pr 0.72), 10 steps at the CFL-0.5 time
+    step of the initial state, FP64: relative max-norm error <= 1e-11."""
+    p = W.tgv_params(32, ma=0.1, re=1600.0, pr=0.72, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    dt = oracle.cfl_dt(p, q0)
+    say("tgv32 10 steps dt", dt)
+    s = hg.Solver(p, q0)
+    assert abs(s.dt() - dt) <= 1e-14 * dt
+    s.step(10, dt)
+    got = s.state()
+    ref, _ = oracle.step(p, q0, 10, dt)
+    err = rel_err(got, ref)
+    say("  state err", err)
+    assert (err <= 1e-11).all(), err
+    st, so = s.stats(), oracle.stats(p, ref)
+    for key in ("Ek", "eps_sol", "eps_com"):
+        assert abs(st[key] - so[key]) <= 1e-11 * abs(so[key]), key
+    assert st["steps"] == 10 and abs(st["t"] - 10 * dt) <= 1e-14
+    s.close()
+
+
+def test_cfl_time_step_mode(hg, oracle):
+    """dt_fixed <= 0: both sides take dt from the CFL rule every step."""
+    p = W.tgv_params((24, 20, 16), ma=0.2, re=800.0, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    s = hg.Solver(p, q0)
+    s.step(3, 0.0)
+    got = s.state()
+    ref, dt_last = oracle.step(p, q0, 3, 0.0)
+    err = rel_err(got, ref)
+    say("cfl mode err", err, "dt", dt_last, s.stats()["dt_last"])
+    assert (err <= 1e-11).all()
+    assert abs(s.stats()["dt_last"] - dt_last) <= 1e-12 * dt_last
+    assert abs(s.dt() - oracle.cfl_dt(p, ref)) <= 1e-12 * dt_last
+    s.close()
+
+
+def test_uniform_flow_bitwise(hg):
+    n = (13, 9, 7)
+    p = W.tgv_params(n, ma=0.5, re=100.0)
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.3), f(0.3), f(-0.2), f(0.1), f(2.0)))
+    s = hg.Solver(p, q0)
+    s.step(3, 0.01)
+    np.testing.assert_array_equal(s.state(), q0)
+    s.close()
+
+
+def test_statistics_parity(hg, oracle):
+    p = W.tgv_params((32, 24, 20))
+    q = W.smooth_random(p, seed=8)
+    s = hg.Solver(p, q)
+    st, so = s.stats(), oracle.stats(p, q)
+    for key in ("Ek", "eps_sol", "eps_dil", "eps_com", "min_p", "min_rho"):
+        assert abs(st[key] - so[key]) <= 1e-12 * abs(so[key]), (key, st[key], so[key])
+    np.testing.assert_allclose(st["total"], so["total"], rtol=1e-12, atol=1e-12 * np.abs(so["total"]).max())
+    np.testing.assert_array_equal(st["max_abs"], so["max_abs"])
+    assert st["nonfinite"] == 0
+    s.close()
+
+
+def test_tgv_initial_statistics_gpu(hg):
+    """P13 on the GPU statistics kernel: E_k = 1/8, eps = (mu/rho0) 3/4 kappa^2."""
+    p = W.tgv_params(32)
+    s = hg.Solver(p, W.tgv_initial(p))
+    st = s.stats()
+    h = 2 * math.pi / 32
+    kap = (8 * math.sin(h) - math.sin(2 * h)) / (6 * h)
+    assert abs(st["Ek"] - 0.125) <= 1e-12
+    assert abs(st["eps_com"] - p["mu_ref"] * 0.75 * kap * kap) <= 1e-12 * p["mu_ref"]
+    s.close()
+
+
+def test_conservation_gpu(hg):
+    p = W.tgv_params((24, 18, 20), ma=0.3, re=200.0)
+    q = W.smooth_random(p, seed=11)
+    s = hg.Solver(p, q)
+    t0 = s.stats()["total"]
+    s.step(5, 0.0)
+    t1 = s.stats()["total"]
+    dv = np.prod([(p["hi"][d] - p["lo"][d]) / p["n"][d] for d in range(3)])
+    scale = np.abs(q).sum(axis=(1, 2, 3)) * dv
+    assert (np.abs(t1 - t0) <= 1e-13 * scale).all(), (t1 - t0) / scale
+    s.close()
+
+
+def test_nonfinite_state_latches(hg):
+    """A NaN planted in the state is reported by hgks_stats and the next
+    hgks_step refuses to advance (forced from the host; no kernel faults)."""
+    p = W.tgv_params(16)
+    q = W.tgv_initial(p)
+    q[0, 3, 4, 5] = np.nan
+    s = hg.Solver(p, q)
+    st = s.stats()
+    assert st["nonfinite"] == 1
+    with pytest.raises(hg.HGKSError) as e:
+        s.step(1, 1e-3)
+    assert e.value.status == hg.HGKS_E_NONFINITE
+    s.close()
+
+
+def test_negative_pressure_latches(hg):
+    p = W.tgv_params(16)
+    q = W.tgv_initial(p)
+    q[4, 2, 2, 2] = 0.0  # zero total energy -> negative pressure
+    s = hg.Solver(p, q)
+    st = s.stats()
+    assert st["min_p"] < 0
+    with pytest.raises(hg.HGKSError) as e:
+        s.step(1, 1e-3)
+    assert e.value.status == hg.HGKS_E_NEGATIVE_STATE
+    s.close()
+
+
+def residual_tolerances(p, q, dt, K=1000.0):
+    """Absolute bounds for |GPU - oracle| in L and dL/dt from the arithmetic.
+
+    Both sides compute the face integrals I(dt) ~ dt |F| to relative rounding
+    error of order eps, in different operation orders (FMA contraction,
+    summation order, libm).  L = -sum dF/h then differs by ~eps |F| / h, and
+    dF/dt = 4 (I(dt) - 2 I(dt/2)) / dt^2 cancels to O(dt^2), so its difference
+    is ~12 eps |F| / dt and dL/dt's is that over h.  K (a few hundred to a
+    thousand rounding steps per face) is the margin; any real defect shows up
+    many orders of magnitude above these bounds."""
+    eps = np.finfo(np.float64).eps
+    rho = q[0]
+    u2 = (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / rho
+    pres = (p["gamma"] - 1.0) * (q[4] - 0.5 * u2)
+    speed = np.sqrt(u2 / rho)
+    fscale = float((pres + u2).max() + (speed * (q[4] + pres)).max() + np.abs(q[1:4]).max())
+    hmin = min((p["hi"][d] - p["lo"][d]) / p["n"][d] for d in range(3))
+    return K * eps * fscale / hmin, 12.0 * K * eps * fscale / (dt * hmin)
+
+
+def test_full_size_sampled_residual(hg, oracle):
+    """At the 256^3 benchmark workload (TGV, Ma 0.29), in the launch
+    configuration the benchmark uses: L and dL/dt at sampled cells (corners,
+    faces of the box, random interior) against the oracle's per-cell values,
+    within the rounding bounds of residual_tolerances."""
+    n = 256
+    p = W.tgv_params(n, ma=0.29, re=1600.0, pr=0.72)
+    q = W.tgv_initial(p)
+    dt = 0.5 * (2 * math.pi / n) / (1.0 + 1.0 / 0.29)
+    say("full-size residual 256^3 dt", dt)
+    s = hg.Solver(p, q)
+    L, dL = s.residual(s.q, dt)
+    rng = np.random.default_rng(256)
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1), (n // 2, 0, n - 1)]
+    cells += [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(60)]
+    idx = np.array(cells)
+    Lg = L[:, idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy().T
+    dLg = dL[:, idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy().T
+    Lmax = L.abs().amax(dim=(1, 2, 3)).cpu().numpy()
+    dLmax = dL.abs().amax(dim=(1, 2, 3)).cpu().numpy()
+    s.close()
+    del L, dL
+    Lo, dLo = oracle.residual_at(p, q, dt, cells)
+    tL, tdL = residual_tolerances(p, q, dt)
+    eL, edL = np.abs(Lg - Lo).max(axis=0), np.abs(dLg - dLo).max(axis=0)
+    say("  sampled abs L err", eL, "bound", tL, "rel to max", eL / Lmax)
+    say("  sampled abs dL err", edL, "bound", tdL, "rel to max", edL / dLmax)
+    assert (eL <= tL).all() and (edL <= tdL).all()
+    # and far below the size of the quantities themselves
+    assert (eL / Lmax <= 1e-10).all() and (edL / dLmax <= 1e-8).all()

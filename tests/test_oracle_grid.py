@@ -154,3 +154,16 @@ def test_density_wave_convergence(oracle):
     oinf = [math.log(errs[i][1] / errs[i + 1][1], 2) for i in range(2)]
     print("density wave L1/Linf errors", errs, "orders", o1, oinf)
     assert o1[-1] >= 3.7 and oinf[-1] >= 3.7, (o1, oinf)
+
+
+def test_residual_at_matches_full_residual(oracle):
+    """The per-cell driver (faces from scratch) reproduces the whole-grid
+    residual bitwise: same arithmetic, different traversal."""
+    p = W.tgv_params((9, 7, 6), ma=0.3, re=300.0)
+    q = W.smooth_random(p, seed=21)
+    L, dL = oracle.residual(p, q, 0.01)
+    cells = [(0, 0, 0), (8, 6, 5), (4, 3, 2), (1, 6, 0)]
+    La, dLa = oracle.residual_at(p, q, 0.01, cells)
+    for c, (i, j, k) in enumerate(cells):
+        np.testing.assert_array_equal(La[c], L[:, k, j, i])
+        np.testing.assert_array_equal(dLa[c], dL[:, k, j, i])
