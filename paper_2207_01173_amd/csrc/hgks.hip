@@ -283,7 +283,6 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
     bi[j] = (size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0]);
   }
   GaussPoint<R> gp(g2);
-  R ql[5], qr[5], dql[3][5], dqr[3][5], dq0n[5];
   const R sn = R(P.dface[DIR][f[DIR]]);
   const R st1 = R(P.dgp[D1][2 * f[D1] + g1]);
   const R st2 = R(P.dgp[D2][2 * f[D2] + g2]);
@@ -293,37 +292,6 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
   rl[2] = qref[1 + D1];
   rl[3] = qref[1 + D2];
   rl[4] = qref[4];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    R v[5], val, der;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_QL + k) * qstride + bi[j]];
-    gauss_value_slope(v, gp, val, der);
-    ql[k] = R(double(val) + rl[k]);
-    dql[2][k] = der * st2;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_QR + k) * qstride + bi[j]];
-    gauss_value_slope(v, gp, val, der);
-    qr[k] = R(double(val) + rl[k]);
-    dqr[2][k] = der * st2;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_DLN + k) * qstride + bi[j]];
-    dql[0][k] = gauss_value(v, gp) * sn;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_DRN + k) * qstride + bi[j]];
-    dqr[0][k] = gauss_value(v, gp) * sn;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_DLT1 + k) * qstride + bi[j]];
-    dql[1][k] = gauss_value(v, gp) * st1;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_DRT1 + k) * qstride + bi[j]];
-    dqr[1][k] = gauss_value(v, gp) * st1;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[(B_D0 + k) * qstride + bi[j]];
-    dq0n[k] = gauss_linear(v, gp) * sn;
-  }
-
-  // ---- kinetic flux at the Gauss point -----------------------------------
   GasParams<R> g;
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
@@ -331,8 +299,74 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
   g.T_ref = R(P.T_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
+  // Five stencil values of quantity qi along t2.
+  auto stencil = [&](int qi, R v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = B[qi * qstride + bi[j]];
+  };
+
+  // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
+  R ql[5], qr[5], tl2[5], tr2[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R v[5], val, der;
+    stencil(B_QL + k, v);
+    gauss_value_slope(v, gp, val, der);
+    ql[k] = R(double(val) + rl[k]);
+    tl2[k] = der * st2;
+    stencil(B_QR + k, v);
+    gauss_value_slope(v, gp, val, der);
+    qr[k] = R(double(val) + rl[k]);
+    tr2[k] = der * st2;
+  }
+  FluxAcc<R> acc;
+  flux_begin(ql, qr, g, R(dt), acc);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // phase 2: left side
+  {
+    R dq[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R v[5];
+      stencil(B_DLN + k, v);
+      dq[0][k] = gauss_value(v, gp) * sn;
+      stencil(B_DLT1 + k, v);
+      dq[1][k] = gauss_value(v, gp) * st1;
+      dq[2][k] = tl2[k];
+    }
+    flux_side<R, true>(ql, dq, g, acc);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // phase 3: right side
+  {
+    R dq[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R v[5];
+      stencil(B_DRN + k, v);
+      dq[0][k] = gauss_value(v, gp) * sn;
+      stencil(B_DRT1 + k, v);
+      dq[1][k] = gauss_value(v, gp) * st1;
+      dq[2][k] = tr2[k];
+    }
+    flux_side<R, false>(qr, dq, g, acc);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // phase 4: equilibrium part and Prandtl correction
   R F1[5], F2[5];
-  gp_flux(ql, qr, dql, dqr, dq0n, g, R(dt), F1, F2);
+  {
+    R dq0n[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R v[5];
+      stencil(B_D0 + k, v);
+      dq0n[k] = gauss_linear(v, gp) * sn;
+    }
+    flux_finish(dq0n, g, acc, F1, F2);
+  }
 
   // ---- 2x2 Gauss sum across the four lanes of the face -------------------
   double s1[5], s2[5];

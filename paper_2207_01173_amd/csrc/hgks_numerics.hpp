@@ -27,15 +27,27 @@ __device__ __forceinline__ void js_smoothness(const R v[5], R b[3]) {
   b[2] = c13 * d2 * d2 + R(0.25) * e2 * e2;
 }
 
-// Nonlinear weights alpha_k = d_k (1 + tau5 / (beta_k + eps)), normalised.
+// Nonlinear weights alpha_k = d_k (1 + tau5 / b_k), b_k = beta_k + eps,
+// normalised.  Multiplying every alpha by b0 b1 b2 leaves the normalised
+// weights unchanged and needs a single reciprocal (FP64: the products stay far
+// from underflow for b >= eps).  The FP32 path keeps one reciprocal per b_k,
+// whose products could underflow.
 template <class R>
 __device__ __forceinline__ void wz_weights(const R b[3], R d0, R d1, R d2, R w[3]) {
   const R eps = WenoEps<R>::v;
-  R t5 = fabs(b[0] - b[2]);
-  R a0 = d0 * (R(1) + t5 / (b[0] + eps));
-  R a1 = d1 * (R(1) + t5 / (b[1] + eps));
-  R a2 = d2 * (R(1) + t5 / (b[2] + eps));
-  R inv = R(1) / (a0 + a1 + a2);
+  const R t5 = fabs(b[0] - b[2]);
+  const R b0 = b[0] + eps, b1 = b[1] + eps, b2 = b[2] + eps;
+  R a0, a1, a2;
+  if (sizeof(R) == 8) {
+    a0 = d0 * (b0 + t5) * (b1 * b2);
+    a1 = d1 * (b1 + t5) * (b0 * b2);
+    a2 = d2 * (b2 + t5) * (b0 * b1);
+  } else {
+    a0 = d0 * (R(1) + t5 / b0);
+    a1 = d1 * (R(1) + t5 / b1);
+    a2 = d2 * (R(1) + t5 / b2);
+  }
+  const R inv = R(1) / (a0 + a1 + a2);
   w[0] = a0 * inv;
   w[1] = a1 * inv;
   w[2] = a2 * inv;
@@ -164,70 +176,135 @@ __device__ __forceinline__ State<R> primitive(const R q[5], R gm1) {
   return s;
 }
 
-template <class R> struct Mom { R u[7], v[7], w[7], x[3]; };
-
-template <class R>
-__device__ __forceinline__ void chain(R mean, R ihl, R m0, R m1, R o[7]) {
-  // ihl = 1/(2 lambda): <c^(n+2)> = mean <c^(n+1)> + (n+1) ihl <c^n>
+// <c^n>, n = 0..N-1, of a Gaussian with the given mean and 1/(2 lambda) = ihl,
+// from the first two: <c^(n+2)> = mean <c^(n+1)> + (n+1) ihl <c^n>.
+template <class R, int N>
+__device__ __forceinline__ void chain(R mean, R ihl, R m0, R m1, R o[N]) {
   o[0] = m0;
   o[1] = m1;
 #pragma unroll
-  for (int n = 0; n < 5; ++n) o[n + 2] = mean * o[n + 1] + R(n + 1) * ihl * o[n];
+  for (int n = 0; n + 2 < N; ++n) o[n + 2] = mean * o[n + 1] + R(n + 1) * ihl * o[n];
 }
 
-// Half-space u-chain for u > 0 (SIDE = +1) or u < 0 (SIDE = -1).
+// Zeroth and first half-space u-moments, u > 0 (SIDE = +1) or u < 0 (SIDE = -1).
 template <class R, int SIDE>
-__device__ __forceinline__ void half_chain(const State<R>& s, R ihl, R o[7]) {
+__device__ __forceinline__ void half_moments01(const State<R>& s, R& m0, R& m1) {
   R sl = sqrt(s.lam);
   R e = exp(-s.lam * s.U * s.U) * R(0.28209479177387814347) / sl;  // e^{-l U^2} / (2 sqrt(pi l))
-  R m0 = R(0.5) * erfc(-R(SIDE) * sl * s.U);
-  R m1 = s.U * m0 + R(SIDE) * e;
-  chain(s.U, ihl, m0, m1, o);
+  m0 = R(0.5) * erfc(-R(SIDE) * sl * s.U);
+  m1 = s.U * m0 + R(SIDE) * e;
 }
+
+// Moments over (v, w, xi) of one Maxwellian, r = v^2 + w^2 + xi^2:
+// E[v^b w^c r^e] for the monomials the flux needs.  The u-direction is kept
+// apart (full or half space), so every moment of a product factorises into a
+// u-moment times one of these.
+template <class R> struct VW {
+  R v, w, r, vv, vw, ww, vr, wr, rr, vvv, vvw, vww, www, vvr, vwr, wwr, vrr, wrr;
+};
 
 template <class R>
-__device__ __forceinline__ void full_tangential(const State<R>& s, R ihl, R K, Mom<R>& m) {
-  chain(s.V, ihl, R(1), s.V, m.v);
-  chain(s.W, ihl, R(1), s.W, m.w);
-  m.x[0] = R(1);
-  m.x[1] = K * ihl;
-  m.x[2] = K * (K + R(2)) * ihl * ihl;
+__device__ __forceinline__ void vw_moments(const State<R>& s, R ihl, R K, VW<R>& e) {
+  R V[6], W[6];
+  chain<R, 6>(s.V, ihl, R(1), s.V, V);
+  chain<R, 6>(s.W, ihl, R(1), s.W, W);
+  const R x1 = K * ihl;                          // <xi^2>
+  const R x2 = K * (K + R(2)) * ihl * ihl;       // <xi^4>
+  e.v = V[1];
+  e.w = W[1];
+  e.r = V[2] + W[2] + x1;
+  e.vv = V[2];
+  e.vw = V[1] * W[1];
+  e.ww = W[2];
+  e.vr = V[3] + V[1] * (W[2] + x1);
+  e.wr = W[3] + W[1] * (V[2] + x1);
+  e.rr = V[4] + W[4] + x2 + R(2) * (V[2] * W[2] + (V[2] + W[2]) * x1);
+  e.vvv = V[3];
+  e.vvw = V[2] * W[1];
+  e.vww = V[1] * W[2];
+  e.www = W[3];
+  e.vvr = V[4] + V[2] * (W[2] + x1);
+  e.vwr = V[3] * W[1] + V[1] * W[3] + V[1] * W[1] * x1;
+  e.wwr = W[4] + W[2] * (V[2] + x1);
+  e.vrr = V[5] + V[1] * (W[4] + x2) + R(2) * (V[3] * W[2] + (V[3] + V[1] * W[2]) * x1);
+  e.wrr = W[5] + W[1] * (V[4] + x2) + R(2) * (V[2] * W[3] + (W[3] + V[2] * W[1]) * x1);
 }
 
-template <class R, int A, int B, int C, int E>
-__device__ __forceinline__ R mono(const Mom<R>& m) {
-  return m.u[A] * m.v[B] * m.w[C] * m.x[E];
-}
+// (v, w, xi)-moments of a polynomial g(v, w, xi^2): E[g], E[v g], E[w g], E[r g].
+template <class R> struct Quad { R e0, ev, ew, er; };
 
-// <u^A v^B w^C (xi^2)^E psi>
-template <class R, int A, int B, int C, int E>
-__device__ __forceinline__ void mpsi(const Mom<R>& m, R o[5]) {
-  o[0] = mono<R, A, B, C, E>(m);
-  o[1] = mono<R, A + 1, B, C, E>(m);
-  o[2] = mono<R, A, B + 1, C, E>(m);
-  o[3] = mono<R, A, B, C + 1, E>(m);
-  o[4] = R(0.5) * (mono<R, A + 2, B, C, E>(m) + mono<R, A, B + 2, C, E>(m) + mono<R, A, B, C + 2, E>(m) +
-                   mono<R, A, B, C, E + 1>(m));
-}
-
-// o (+)= <(a . psi) u^A v^B w^C psi>
-template <class R, int A, int B, int C, bool ACC>
-__device__ __forceinline__ void mapsi(const Mom<R>& m, const R a[5], R o[5]) {
-  R t0[5], t1[5], t2[5], t3[5], s0[5], s1[5], s2[5], s3[5];
-  mpsi<R, A, B, C, 0>(m, t0);
-  mpsi<R, A + 1, B, C, 0>(m, t1);
-  mpsi<R, A, B + 1, C, 0>(m, t2);
-  mpsi<R, A, B, C + 1, 0>(m, t3);
-  mpsi<R, A + 2, B, C, 0>(m, s0);
-  mpsi<R, A, B + 2, C, 0>(m, s1);
-  mpsi<R, A, B, C + 2, 0>(m, s2);
-  mpsi<R, A, B, C, 1>(m, s3);
+// For a moment coefficient vector a, a . psi = p + a1 u + h u^2 with
+// p = a0 + a2 v + a3 w + h r and h = a4 / 2.  Quad of p times 1, v or w:
+template <class R>
+__device__ __forceinline__ Quad<R> quad_p(const R a[5], const VW<R>& e) {
   const R h = R(0.5) * a[4];
+  return {a[0] + a[2] * e.v + a[3] * e.w + h * e.r, a[0] * e.v + a[2] * e.vv + a[3] * e.vw + h * e.vr,
+          a[0] * e.w + a[2] * e.vw + a[3] * e.ww + h * e.wr, a[0] * e.r + a[2] * e.vr + a[3] * e.wr + h * e.rr};
+}
+template <class R>
+__device__ __forceinline__ Quad<R> quad_vp(const R a[5], const VW<R>& e) {
+  const R h = R(0.5) * a[4];
+  return {a[0] * e.v + a[2] * e.vv + a[3] * e.vw + h * e.vr, a[0] * e.vv + a[2] * e.vvv + a[3] * e.vvw + h * e.vvr,
+          a[0] * e.vw + a[2] * e.vvw + a[3] * e.vww + h * e.vwr, a[0] * e.vr + a[2] * e.vvr + a[3] * e.vwr + h * e.vrr};
+}
+template <class R>
+__device__ __forceinline__ Quad<R> quad_wp(const R a[5], const VW<R>& e) {
+  const R h = R(0.5) * a[4];
+  return {a[0] * e.w + a[2] * e.vw + a[3] * e.ww + h * e.wr, a[0] * e.vw + a[2] * e.vvw + a[3] * e.vww + h * e.vwr,
+          a[0] * e.ww + a[2] * e.vww + a[3] * e.www + h * e.wwr, a[0] * e.wr + a[2] * e.vwr + a[3] * e.wwr + h * e.wrr};
+}
+// Quad of c (1, v, w, r-weighted): c times the unit polynomial.
+template <class R>
+__device__ __forceinline__ Quad<R> quad_c(R c, const VW<R>& e) {
+  return {c, c * e.v, c * e.w, c * e.r};
+}
+// Quad of c0 + c1 v + c2 w (tangential-linear polynomial).
+template <class R>
+__device__ __forceinline__ Quad<R> quad_lin(R c0, R c1, R c2, const VW<R>& e) {
+  return {c0 + c1 * e.v + c2 * e.w, c0 * e.v + c1 * e.vv + c2 * e.vw, c0 * e.w + c1 * e.vw + c2 * e.ww,
+          c0 * e.r + c1 * e.vr + c2 * e.wr};
+}
+template <class R>
+__device__ __forceinline__ Quad<R> qadd(const Quad<R>& a, const Quad<R>& b) {
+  return {a.e0 + b.e0, a.ev + b.ev, a.ew + b.ew, a.er + b.er};
+}
+
+// <u^X G psi> for G = sum_{i < NS} u^i g_i, given the quads of the g_i and a
+// u-moment table Mu (full or half space), psi = (1, u, v, w, (u^2 + r)/2).
+template <class R, int X, int NS>
+__device__ __forceinline__ void assemble(const Quad<R> q[NS], const R Mu[7], R o[5]) {
+  R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0), a4 = R(0);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    R r = a[0] * t0[k] + a[1] * t1[k] + a[2] * t2[k] + a[3] * t3[k] + h * (s0[k] + s1[k] + s2[k] + s3[k]);
-    o[k] = ACC ? o[k] + r : r;
+  for (int i = 0; i < NS; ++i) {
+    a0 += Mu[X + i] * q[i].e0;
+    a1 += Mu[X + i + 1] * q[i].e0;
+    a2 += Mu[X + i] * q[i].ev;
+    a3 += Mu[X + i] * q[i].ew;
+    a4 += Mu[X + i + 2] * q[i].e0 + Mu[X + i] * q[i].er;
   }
+  o[0] = a0;
+  o[1] = a1;
+  o[2] = a2;
+  o[3] = a3;
+  o[4] = R(0.5) * a4;
+}
+
+// u-series of a . psi: (p, a1, h).
+template <class R>
+__device__ __forceinline__ void series_apsi(const R a[5], const VW<R>& e, Quad<R> q[3]) {
+  q[0] = quad_p(a, e);
+  q[1] = quad_c(a[1], e);
+  q[2] = quad_c(R(0.5) * a[4], e);
+}
+
+// u-series of Pi = u (an . psi) + v (at1 . psi) + w (at2 . psi):
+// Pi_0 = v p_t1 + w p_t2, Pi_1 = p_n + at1_1 v + at2_1 w, Pi_2 = an_1 + h_t1 v + h_t2 w, Pi_3 = h_n.
+template <class R>
+__device__ __forceinline__ void series_pi(const R a[3][5], const VW<R>& e, Quad<R> q[4]) {
+  q[0] = qadd(quad_vp(a[1], e), quad_wp(a[2], e));
+  q[1] = qadd(quad_p(a[0], e), quad_lin(R(0), a[1][1], a[2][1], e));
+  q[2] = quad_lin(a[0][1], R(0.5) * a[1][4], R(0.5) * a[2][4], e);
+  q[3] = quad_c(R(0.5) * a[0][4], e);
 }
 
 // Closed-form solution of <(a . psi) psi> = b for a Maxwellian state.
@@ -275,29 +352,75 @@ __device__ __forceinline__ void time_integrals(R tau, R delta, R C[6]) {
   }
 }
 
-// Scalar part of the heat-flux correction: for a moment vector v of psi,
-// v_E - U0 . v_m + |U0|^2/2 v_rho (energy in the frame of U0).
+// Energy in the frame of U0 carried by a moment vector of psi:
+// v_E - U0 . v_m + |U0|^2/2 v_rho.
 template <class R>
 __device__ __forceinline__ R thermal(const R v[5], R U, R V, R W, R hu2) {
   return v[4] - (U * v[1] + V * v[2] + W * v[3]) + hu2 * v[0];
 }
 
-// Contributions of one non-equilibrium side (g_l with u > 0 or g_r with u < 0):
-// flux moments weighted by C4, C5, C6 and the moments W of the same terms used
-// by the Prandtl correction; also the side's part of the tangential slopes of
-// Q0 (exact derivative of the compatibility map).
-template <class R, int SIDE>
-__device__ __forceinline__ void side_terms(const R q[5], const R dq[3][5], const GasParams<R>& g,
-                                           const R C1[6], const R C2[6], R U0, R V0, R W0, R hu2,
-                                           R F1[5], R F2[5], R& w1, R& w2, R dq0t[2][5]) {
+// Running state of one Gauss-point flux evaluation, filled in phases so that
+// the caller can reconstruct the left inputs, consume them, then the right
+// ones, keeping few values live at a time.
+template <class R> struct FluxAcc {
+  State<R> s0;          // interface equilibrium
+  R ihl0, hu2;          // 1/(2 lambda0), |U0|^2 / 2
+  R C1[6], C2[6];       // time integrals over [0, dt] and [0, dt/2]
+  R lm0, lm1, rm0, rm1; // half-space zeroth/first u-moments of the left/right states
+  R F1[5], F2[5];       // time-integrated flux, both windows
+  R w1, w2;             // thermal part of the conserved-variable integrals (Prandtl correction)
+  R dq0t[2][5];         // tangential slopes of Q0 (exact derivative of the compatibility map)
+};
+
+// Phase 1: equilibrium at the interface from the compatibility condition,
+// Q0 = rho_l <psi>_{u>0, l} + rho_r <psi>_{u<0, r}, collision time and the
+// time integrals.
+template <class R>
+__device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const GasParams<R>& g, R dt, FluxAcc<R>& A) {
+  R q0[5];
+  {
+    const State<R> sl = primitive(ql, g.gm1), sr = primitive(qr, g.gm1);
+    half_moments01<R, 1>(sl, A.lm0, A.lm1);
+    half_moments01<R, -1>(sr, A.rm0, A.rm1);
+    const R il = R(0.5) / sl.lam, ir = R(0.5) / sr.lam;
+    // <psi> with half-space u: (m0, m1, V m0, W m0, (m2 + m0 (V^2 + W^2 + (K + 2) ihl)) / 2)
+    const R l2 = sl.U * A.lm1 + il * A.lm0, r2 = sr.U * A.rm1 + ir * A.rm0;
+    const R lt = sl.V * sl.V + sl.W * sl.W + (g.K + R(2)) * il;
+    const R rt = sr.V * sr.V + sr.W * sr.W + (g.K + R(2)) * ir;
+    q0[0] = sl.rho * A.lm0 + sr.rho * A.rm0;
+    q0[1] = sl.rho * A.lm1 + sr.rho * A.rm1;
+    q0[2] = sl.rho * sl.V * A.lm0 + sr.rho * sr.V * A.rm0;
+    q0[3] = sl.rho * sl.W * A.lm0 + sr.rho * sr.W * A.rm0;
+    q0[4] = R(0.5) * (sl.rho * (l2 + A.lm0 * lt) + sr.rho * (r2 + A.rm0 * rt));
+  }
+  A.s0 = primitive(q0, g.gm1);
+  A.ihl0 = R(0.5) / A.s0.lam;
+  // collision time tau = mu(T0) / p0, T0 = p0/rho0 = 1/(2 lambda0)
+  const R p0 = A.s0.rho * A.ihl0;
+  R mu = g.mu_ref;
+  if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 / g.T_ref, g.mu_exp);
+  const R tau = mu / p0;
+  time_integrals(tau, dt, A.C1);
+  time_integrals(tau, R(0.5) * dt, A.C2);
+  A.hu2 = R(0.5) * (A.s0.U * A.s0.U + A.s0.V * A.s0.V + A.s0.W * A.s0.W);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) { A.F1[k] = R(0); A.F2[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
+  A.w1 = R(0);
+  A.w2 = R(0);
+}
+
+// Phase 2/3: contributions of one non-equilibrium side (g_l with u > 0 when
+// LEFT, g_r with u < 0 otherwise): flux moments weighted by C4, C5, C6, the
+// thermal part of the same terms' conserved-variable moments, and the side's
+// part of the tangential slopes of Q0.
+template <class R, bool LEFT>
+__device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const GasParams<R>& g, FluxAcc<R>& Acc) {
   State<R> s = primitive(q, g.gm1);
-  R ihl = R(0.5) / s.lam;
-  Mom<R> m;
-  full_tangential(s, ihl, g.K, m);
-  // full u-chain first, for the time slope
-  chain(s.U, ihl, R(1), s.U, m.u);
-  R a[3][5], A[5];
-  R ir = R(1) / s.rho;
+  const R ihl = R(0.5) / s.lam;
+  VW<R> e;
+  vw_moments(s, ihl, g.K, e);
+  R a[3][5];
+  const R ir = R(1) / s.rho;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     R b[5];
@@ -305,45 +428,120 @@ __device__ __forceinline__ void side_terms(const R q[5], const R dq[3][5], const
     for (int k = 0; k < 5; ++k) b[k] = dq[d][k] * ir;
     slope_solve(s, ihl, g.K, b, a[d]);
   }
+  Quad<R> pi[4];
+  series_pi(a, e, pi);
+  R A[5];
+  {
+    R Mf[7], T[5];
+    chain<R, 7>(s.U, ihl, R(1), s.U, Mf);
+    assemble<R, 0, 4>(pi, Mf, T);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) T[k] = -T[k];
+    slope_solve(s, ihl, g.K, T, A);
+  }
+  R Mh[7];
+  if (LEFT) chain<R, 7>(s.U, ihl, Acc.lm0, Acc.lm1, Mh);
+  else chain<R, 7>(s.U, ihl, Acc.rm0, Acc.rm1, Mh);
+  const Quad<R> unit[1] = {quad_c(R(1), e)};
+  Quad<R> qa[3];
+  series_apsi(A, e, qa);
+  const R rho = s.rho;
+  const R U0 = Acc.s0.U, V0 = Acc.s0.V, W0 = Acc.s0.W;
+  {
+    R X1[5], X2[5], X3[5];
+    assemble<R, 1, 1>(unit, Mh, X1);
+    assemble<R, 1, 4>(pi, Mh, X2);
+    assemble<R, 1, 3>(qa, Mh, X3);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      Acc.F1[k] += rho * (Acc.C1[3] * X1[k] + Acc.C1[4] * X2[k] + Acc.C1[5] * X3[k]);
+      Acc.F2[k] += rho * (Acc.C2[3] * X1[k] + Acc.C2[4] * X2[k] + Acc.C2[5] * X3[k]);
+    }
+  }
+  {
+    R Y[5];
+    assemble<R, 0, 1>(unit, Mh, Y);
+    const R y1 = thermal(Y, U0, V0, W0, Acc.hu2);
+    assemble<R, 0, 4>(pi, Mh, Y);
+    const R y2 = thermal(Y, U0, V0, W0, Acc.hu2);
+    assemble<R, 0, 3>(qa, Mh, Y);
+    const R y3 = thermal(Y, U0, V0, W0, Acc.hu2);
+    Acc.w1 += rho * (Acc.C1[3] * y1 + Acc.C1[4] * y2 + Acc.C1[5] * y3);
+    Acc.w2 += rho * (Acc.C2[3] * y1 + Acc.C2[4] * y2 + Acc.C2[5] * y3);
+  }
+#pragma unroll
+  for (int d = 1; d < 3; ++d) {
+    Quad<R> qt[3];
+    series_apsi(a[d], e, qt);
+    R t[5];
+    assemble<R, 0, 3>(qt, Mh, t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Acc.dq0t[d - 1][k] += rho * t[k];
+  }
+}
+
+// Phase 4: equilibrium part with the normal slope of Q0 (dq0n) and the
+// accumulated tangential ones, then the Prandtl correction of the energy
+// flux, q = thermal(F) - U0_n thermal(W).
+template <class R>
+__device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>& g, FluxAcc<R>& Acc, R F1[5],
+                                            R F2[5]) {
+  const State<R>& s0 = Acc.s0;
+  const R ihl0 = Acc.ihl0;
+  VW<R> e;
+  vw_moments(s0, ihl0, g.K, e);
+  R Mf[7];
+  chain<R, 7>(s0.U, ihl0, R(1), s0.U, Mf);
+  R a[3][5];
+  const R ir = R(1) / s0.rho;
   {
     R b[5];
-    mapsi<R, 1, 0, 0, false>(m, a[0], b);
-    mapsi<R, 0, 1, 0, true>(m, a[1], b);
-    mapsi<R, 0, 0, 1, true>(m, a[2], b);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = -b[k];
-    slope_solve(s, ihl, g.K, b, A);
+    for (int k = 0; k < 5; ++k) b[k] = dq0n[k] * ir;
+    slope_solve(s0, ihl0, g.K, b, a[0]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[0][k] * ir;
+    slope_solve(s0, ihl0, g.K, b, a[1]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[1][k] * ir;
+    slope_solve(s0, ihl0, g.K, b, a[2]);
   }
-  // switch to the half-space u-chain
-  half_chain<R, SIDE>(s, ihl, m.u);
+  Quad<R> pi[4];
+  series_pi(a, e, pi);
+  R T[5];  // sum_d <s_d (a_d . psi) psi>_0
+  assemble<R, 0, 4>(pi, Mf, T);
+  R A[5];
+  {
+    R b[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) b[k] = -T[k];
+    slope_solve(s0, ihl0, g.K, b, A);
+  }
+  const Quad<R> unit[1] = {quad_c(R(1), e)};
+  Quad<R> qa[3];
+  series_apsi(A, e, qa);
+  const R rho = s0.rho;
   R X1[5], X2[5], X3[5];
-  mpsi<R, 1, 0, 0, 0>(m, X1);
-  mapsi<R, 2, 0, 0, false>(m, a[0], X2);
-  mapsi<R, 1, 1, 0, true>(m, a[1], X2);
-  mapsi<R, 1, 0, 1, true>(m, a[2], X2);
-  mapsi<R, 1, 0, 0, false>(m, A, X3);
-  const R rho = s.rho;
+  assemble<R, 1, 1>(unit, Mf, X1);
+  assemble<R, 1, 4>(pi, Mf, X2);
+  assemble<R, 1, 3>(qa, Mf, X3);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    F1[k] += rho * (C1[3] * X1[k] + C1[4] * X2[k] + C1[5] * X3[k]);
-    F2[k] += rho * (C2[3] * X1[k] + C2[4] * X2[k] + C2[5] * X3[k]);
+    F1[k] = Acc.F1[k] + rho * (Acc.C1[0] * X1[k] + Acc.C1[1] * X2[k] + Acc.C1[2] * X3[k]);
+    F2[k] = Acc.F2[k] + rho * (Acc.C2[0] * X1[k] + Acc.C2[1] * X2[k] + Acc.C2[2] * X3[k]);
   }
-  R Y1[5], Y2[5], Y3[5];
-  mpsi<R, 0, 0, 0, 0>(m, Y1);
-  mapsi<R, 1, 0, 0, false>(m, a[0], Y2);
-  mapsi<R, 0, 1, 0, true>(m, a[1], Y2);
-  mapsi<R, 0, 0, 1, true>(m, a[2], Y2);
-  mapsi<R, 0, 0, 0, false>(m, A, Y3);
-  R y1 = thermal(Y1, U0, V0, W0, hu2), y2 = thermal(Y2, U0, V0, W0, hu2), y3 = thermal(Y3, U0, V0, W0, hu2);
-  w1 += rho * (C1[3] * y1 + C1[4] * y2 + C1[5] * y3);
-  w2 += rho * (C2[3] * y1 + C2[4] * y2 + C2[5] * y3);
-  R t[5];
-  mapsi<R, 0, 0, 0, false>(m, a[1], t);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) dq0t[0][k] += rho * t[k];
-  mapsi<R, 0, 0, 0, false>(m, a[2], t);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) dq0t[1][k] += rho * t[k];
+  R Y[5];
+  assemble<R, 0, 1>(unit, Mf, Y);
+  const R y1 = thermal(Y, s0.U, s0.V, s0.W, Acc.hu2);
+  const R y2 = thermal(T, s0.U, s0.V, s0.W, Acc.hu2);
+  assemble<R, 0, 3>(qa, Mf, Y);
+  const R y3 = thermal(Y, s0.U, s0.V, s0.W, Acc.hu2);
+  const R w1 = Acc.w1 + rho * (Acc.C1[0] * y1 + Acc.C1[1] * y2 + Acc.C1[2] * y3);
+  const R w2 = Acc.w2 + rho * (Acc.C2[0] * y1 + Acc.C2[1] * y2 + Acc.C2[2] * y3);
+  const R qh1 = thermal(F1, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * w1;
+  const R qh2 = thermal(F2, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * w2;
+  F1[4] += g.pr_fix * qh1;
+  F2[4] += g.pr_fix * qh2;
 }
 
 // Time-integrated flux at one Gauss point, local frame (n, t1, t2), for the
@@ -351,101 +549,11 @@ __device__ __forceinline__ void side_terms(const R q[5], const R dq[3][5], const
 template <class R>
 __device__ __forceinline__ void gp_flux(const R ql[5], const R qr[5], const R dql[3][5], const R dqr[3][5],
                                         const R dq0n[5], const GasParams<R>& g, R dt, R F1[5], R F2[5]) {
-  // interface equilibrium from the compatibility condition
-  R q0[5];
-  {
-    State<R> sl = primitive(ql, g.gm1), sr = primitive(qr, g.gm1);
-    Mom<R> m;
-    R ihl = R(0.5) / sl.lam;
-    full_tangential(sl, ihl, g.K, m);
-    half_chain<R, 1>(sl, ihl, m.u);
-    R h[5];
-    mpsi<R, 0, 0, 0, 0>(m, h);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) q0[k] = sl.rho * h[k];
-    ihl = R(0.5) / sr.lam;
-    full_tangential(sr, ihl, g.K, m);
-    half_chain<R, -1>(sr, ihl, m.u);
-    mpsi<R, 0, 0, 0, 0>(m, h);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) q0[k] += sr.rho * h[k];
-  }
-  State<R> s0 = primitive(q0, g.gm1);
-  R ihl0 = R(0.5) / s0.lam;
-  // collision time tau = mu(T0) / p0, T0 = p0/rho0 = 1/(2 lambda0)
-  R p0 = s0.rho * ihl0;
-  R mu = g.mu_ref;
-  if (g.mu_exp != R(0)) mu = g.mu_ref * pow(ihl0 / g.T_ref, g.mu_exp);
-  R tau = mu / p0;
-  R C1[6], C2[6];
-  time_integrals(tau, dt, C1);
-  time_integrals(tau, R(0.5) * dt, C2);
-  R hu2 = R(0.5) * (s0.U * s0.U + s0.V * s0.V + s0.W * s0.W);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) { F1[k] = R(0); F2[k] = R(0); }
-  R w1 = R(0), w2 = R(0);
-  R dq0t[2][5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) { dq0t[0][k] = R(0); dq0t[1][k] = R(0); }
-  side_terms<R, 1>(ql, dql, g, C1, C2, s0.U, s0.V, s0.W, hu2, F1, F2, w1, w2, dq0t);
-  side_terms<R, -1>(qr, dqr, g, C1, C2, s0.U, s0.V, s0.W, hu2, F1, F2, w1, w2, dq0t);
-  // equilibrium part
-  {
-    Mom<R> m;
-    full_tangential(s0, ihl0, g.K, m);
-    chain(s0.U, ihl0, R(1), s0.U, m.u);
-    R a[3][5], A[5];
-    R ir = R(1) / s0.rho;
-    {
-      R b[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = dq0n[k] * ir;
-      slope_solve(s0, ihl0, g.K, b, a[0]);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = dq0t[0][k] * ir;
-      slope_solve(s0, ihl0, g.K, b, a[1]);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = dq0t[1][k] * ir;
-      slope_solve(s0, ihl0, g.K, b, a[2]);
-    }
-    R Y2[5];  // sum_d <s_d (a_d . psi) psi>_0
-    mapsi<R, 1, 0, 0, false>(m, a[0], Y2);
-    mapsi<R, 0, 1, 0, true>(m, a[1], Y2);
-    mapsi<R, 0, 0, 1, true>(m, a[2], Y2);
-    {
-      R b[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = -Y2[k];
-      slope_solve(s0, ihl0, g.K, b, A);
-    }
-    R X1[5], X2[5], X3[5];
-    mpsi<R, 1, 0, 0, 0>(m, X1);
-    mapsi<R, 2, 0, 0, false>(m, a[0], X2);
-    mapsi<R, 1, 1, 0, true>(m, a[1], X2);
-    mapsi<R, 1, 0, 1, true>(m, a[2], X2);
-    mapsi<R, 1, 0, 0, false>(m, A, X3);
-    const R rho = s0.rho;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      F1[k] += rho * (C1[0] * X1[k] + C1[1] * X2[k] + C1[2] * X3[k]);
-      F2[k] += rho * (C2[0] * X1[k] + C2[1] * X2[k] + C2[2] * X3[k]);
-    }
-    // W-moments of the equilibrium terms: <psi>_0, Y2 and <A psi>_0 = -Y2
-    R Y1[5];
-    mpsi<R, 0, 0, 0, 0>(m, Y1);
-    R Y3[5];
-    mapsi<R, 0, 0, 0, false>(m, A, Y3);
-    R y1 = thermal(Y1, s0.U, s0.V, s0.W, hu2);
-    R y2 = thermal(Y2, s0.U, s0.V, s0.W, hu2);
-    R y3 = thermal(Y3, s0.U, s0.V, s0.W, hu2);
-    w1 += rho * (C1[0] * y1 + C1[1] * y2 + C1[2] * y3);
-    w2 += rho * (C2[0] * y1 + C2[1] * y2 + C2[2] * y3);
-  }
-  // Prandtl correction of the energy flux: q = thermal(F) - U0_n thermal(W)
-  R qh1 = thermal(F1, s0.U, s0.V, s0.W, hu2) - s0.U * w1;
-  R qh2 = thermal(F2, s0.U, s0.V, s0.W, hu2) - s0.U * w2;
-  F1[4] += g.pr_fix * qh1;
-  F2[4] += g.pr_fix * qh2;
+  FluxAcc<R> A;
+  flux_begin(ql, qr, g, dt, A);
+  flux_side<R, true>(ql, dql, g, A);
+  flux_side<R, false>(qr, dqr, g, A);
+  flux_finish(dq0n, g, A, F1, F2);
 }
 
 }  // namespace hgks

@@ -11,7 +11,7 @@ def test_flop_constants_match_oracle(oracle):
     import bench
 
     c = oracle.count_flops()
-    flux = 4 * (c["tangential_2_per_gp"] + c["flux_per_gp"]) + c["face_assembly"]
+    flux = 4 * (c["tangential_2_per_gp"] + c["flux_per_gp_lean"]) + c["face_assembly"]
     recon = c["normal_sweep_per_face"] + 2 * c["tangential_1_per_face_gp_line"]
     assert bench.FLOPS_FLUX_PER_FACE == flux
     assert bench.FLOPS_RECON_PER_FACE == recon

@@ -244,3 +244,19 @@ def test_chapman_enskog_heat_flux(oracle, Pr):
     Fn = (4 * F2 - F1) / dt
     ref = -gamma / (gamma - 1) * mu / Pr * dTdx
     assert abs(Fn[4] - ref) <= 1e-11 * abs(ref), (Fn[4], ref)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("mu,Pr", [(0.0, 1.0), (2e-3, 0.72), (0.5, 0.7)])
+def test_lean_flux_equals_plain_flux(oracle, seed, mu, Pr):
+    """The economical evaluation (u separated from v, w, xi) whose operations
+    define the algorithmic FLOP count returns the plain evaluation's flux."""
+    rng = np.random.default_rng(seed)
+    ql = _q_of((1.0 + 0.1 * rng.uniform(-1, 1), *rng.uniform(-0.5, 0.5, 3), 0.5 + 0.3 * rng.uniform()))
+    qr = _q_of((1.0 + 0.1 * rng.uniform(-1, 1), *rng.uniform(-0.5, 0.5, 3), 0.5 + 0.3 * rng.uniform()))
+    dql, dqr = rng.uniform(-0.3, 0.3, (3, 5)), rng.uniform(-0.3, 0.3, (3, 5))
+    dq0n = rng.uniform(-0.3, 0.3, 5)
+    a1, a2 = oracle.gp_flux(ql, qr, dql, dqr, dq0n, mu_ref=mu, Pr=Pr, dt1=0.02, dt2=0.01)
+    b1, b2 = oracle.gp_flux_lean(ql, qr, dql, dqr, dq0n, mu_ref=mu, Pr=Pr, dt1=0.02, dt2=0.01)
+    np.testing.assert_allclose(b1, a1, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(b2, a2, rtol=1e-12, atol=1e-14)
