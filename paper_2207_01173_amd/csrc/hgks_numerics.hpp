@@ -15,16 +15,37 @@ template <class R> struct WenoEps;
 template <> struct WenoEps<double> { static constexpr double v = 1e-20; };
 template <> struct WenoEps<float> { static constexpr float v = 1e-20f; };
 
-// Jiang-Shu smoothness indicators of the three quadratic candidates.
+// Reciprocal of a positive, normal number: the hardware estimate refined by
+// two Newton steps (a few ulp at most in FP64; the FP32 path uses 1/x).
+template <class R> __device__ __forceinline__ R pos_rcp(R x);
+template <> __device__ __forceinline__ double pos_rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+template <> __device__ __forceinline__ float pos_rcp<float>(float x) { return 1.0f / x; }
+
+// The three quadratic candidates through averages (v0,v1,v2), (v1,v2,v3),
+// (v2,v3,v4), written about the centre cell (x in [-1/2, 1/2]) as
+// p_k(x) = v2 - c_k/24 + b_k x + c_k x^2 / 2: c_k is the candidate's second
+// difference, b_k its slope at the centre.  The Jiang-Shu smoothness
+// indicators are then beta_k = 13/12 c_k^2 + b_k^2.
+template <class R> struct Candidates { R c[3], b[3], beta[3]; };
+
 template <class R>
-__device__ __forceinline__ void js_smoothness(const R v[5], R b[3]) {
+__device__ __forceinline__ Candidates<R> candidates(const R v[5]) {
+  Candidates<R> k;
+  k.c[0] = v[0] - R(2) * v[1] + v[2];
+  k.b[0] = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
+  k.c[1] = v[1] - R(2) * v[2] + v[3];
+  k.b[1] = R(0.5) * (v[3] - v[1]);
+  k.c[2] = v[2] - R(2) * v[3] + v[4];
+  k.b[2] = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
   const R c13 = R(13.0 / 12.0);
-  R d0 = v[0] - R(2) * v[1] + v[2], e0 = v[0] - R(4) * v[1] + R(3) * v[2];
-  R d1 = v[1] - R(2) * v[2] + v[3], e1 = v[1] - v[3];
-  R d2 = v[2] - R(2) * v[3] + v[4], e2 = R(3) * v[2] - R(4) * v[3] + v[4];
-  b[0] = c13 * d0 * d0 + R(0.25) * e0 * e0;
-  b[1] = c13 * d1 * d1 + R(0.25) * e1 * e1;
-  b[2] = c13 * d2 * d2 + R(0.25) * e2 * e2;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k.beta[i] = c13 * k.c[i] * k.c[i] + k.b[i] * k.b[i];
+  return k;
 }
 
 // Nonlinear weights alpha_k = d_k (1 + tau5 / b_k), b_k = beta_k + eps,
@@ -33,10 +54,10 @@ __device__ __forceinline__ void js_smoothness(const R v[5], R b[3]) {
 // from underflow for b >= eps).  The FP32 path keeps one reciprocal per b_k,
 // whose products could underflow.
 template <class R>
-__device__ __forceinline__ void wz_weights(const R b[3], R d0, R d1, R d2, R w[3]) {
+__device__ __forceinline__ void wz_weights(const R beta[3], R d0, R d1, R d2, R w[3]) {
   const R eps = WenoEps<R>::v;
-  const R t5 = fabs(b[0] - b[2]);
-  const R b0 = b[0] + eps, b1 = b[1] + eps, b2 = b[2] + eps;
+  const R t5 = fabs(beta[0] - beta[2]);
+  const R b0 = beta[0] + eps, b1 = beta[1] + eps, b2 = beta[2] + eps;
   R a0, a1, a2;
   if (sizeof(R) == 8) {
     a0 = d0 * (b0 + t5) * (b1 * b2);
@@ -47,7 +68,7 @@ __device__ __forceinline__ void wz_weights(const R b[3], R d0, R d1, R d2, R w[3
     a1 = d1 * (R(1) + t5 / b1);
     a2 = d2 * (R(1) + t5 / b2);
   }
-  const R inv = R(1) / (a0 + a1 + a2);
+  const R inv = pos_rcp(a0 + a1 + a2);
   w[0] = a0 * inv;
   w[1] = a1 * inv;
   w[2] = a2 * inv;
@@ -79,69 +100,49 @@ template <class R> struct GaussPoint {
   }
 };
 
-// Candidate values and slopes (per unit index) at a Gauss point.
-template <class R>
-__device__ __forceinline__ void gauss_candidates(const R v[5], R s, R p[3], R dp[3]) {
-  // quadratic through three averages: value a + b s at the Gauss point (the
-  // s^2 = 1/12 term cancels the 1/12 offset of the averages), slope b + 2 c s
-  R c0 = v[0] - R(2) * v[1] + v[2];
-  R b0 = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
-  R c1 = v[1] - R(2) * v[2] + v[3];
-  R b1 = R(0.5) * (v[3] - v[1]);
-  R c2 = v[2] - R(2) * v[3] + v[4];
-  R b2 = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
-  p[0] = v[2] + b0 * s;
-  p[1] = v[2] + b1 * s;
-  p[2] = v[2] + b2 * s;
-  dp[0] = b0 + c0 * s;
-  dp[1] = b1 + c1 * s;
-  dp[2] = b2 + c2 * s;
-}
+// At a Gauss point (s^2 = 1/12) the candidate value is v2 + b_k s and its
+// slope b_k + c_k s.
 
 // WENO-Z value at a Gauss point.
 template <class R>
 __device__ __forceinline__ R gauss_value(const R v[5], const GaussPoint<R>& gp) {
-  R b[3], w[3], p[3], dp[3];
-  js_smoothness(v, b);
-  wz_weights(b, gp.dv0, gp.dv1, gp.dv2, w);
-  gauss_candidates(v, gp.s, p, dp);
-  return w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
+  const Candidates<R> k = candidates(v);
+  R w[3];
+  wz_weights(k.beta, gp.dv0, gp.dv1, gp.dv2, w);
+  return v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
 }
 
 // WENO-Z value and slope at a Gauss point (slope with the slope weights).
 template <class R>
 __device__ __forceinline__ void gauss_value_slope(const R v[5], const GaussPoint<R>& gp, R& val, R& der) {
-  R b[3], w[3], p[3], dp[3];
-  js_smoothness(v, b);
-  gauss_candidates(v, gp.s, p, dp);
-  wz_weights(b, gp.dv0, gp.dv1, gp.dv2, w);
-  val = w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
-  wz_weights(b, gp.dd0, gp.dd1, gp.dd2, w);
-  der = w[0] * dp[0] + w[1] * dp[1] + w[2] * dp[2];
+  const Candidates<R> k = candidates(v);
+  R w[3];
+  wz_weights(k.beta, gp.dv0, gp.dv1, gp.dv2, w);
+  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_weights(k.beta, gp.dd0, gp.dd1, gp.dd2, w);
+  der = w[0] * (k.b[0] + k.c[0] * gp.s) + w[1] * (k.b[1] + k.c[1] * gp.s) + w[2] * (k.b[2] + k.c[2] * gp.s);
 }
 
 // Linear (fifth-order) value at a Gauss point: the quartic through the averages.
 template <class R>
 __device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp) {
-  R p[3], dp[3];
-  gauss_candidates(v, gp.s, p, dp);
-  return gp.dv0 * p[0] + gp.dv1 * p[1] + gp.dv2 * p[2];
+  const R b0 = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
+  const R b1 = R(0.5) * (v[3] - v[1]);
+  const R b2 = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
+  return v[2] + gp.s * (gp.dv0 * b0 + gp.dv1 * b1 + gp.dv2 * b2);
 }
 
-// Value and slope at the right face (s = 1/2) of the centre cell.
+// Value and slope at the right face (s = 1/2) of the centre cell: candidate
+// value v2 + b_k/2 + c_k/12, slope b_k + c_k/2.
 template <class R>
 __device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
-  R b[3], w[3];
-  js_smoothness(v, b);
-  wz_weights(b, R(0.1), R(0.6), R(0.3), w);
-  const R sixth = R(1.0 / 6.0);
-  R p0 = (R(2) * v[0] - R(7) * v[1] + R(11) * v[2]) * sixth;
-  R p1 = (R(5) * v[2] - v[1] + R(2) * v[3]) * sixth;
-  R p2 = (R(2) * v[2] + R(5) * v[3] - v[4]) * sixth;
-  R s0 = v[0] - R(3) * v[1] + R(2) * v[2];
-  R s12 = v[3] - v[2];
-  val = w[0] * p0 + w[1] * p1 + w[2] * p2;
-  der = w[0] * s0 + (w[1] + w[2]) * s12;
+  const Candidates<R> k = candidates(v);
+  R w[3];
+  wz_weights(k.beta, R(0.1), R(0.6), R(0.3), w);
+  const R twelfth = R(1.0 / 12.0);
+  val = v[2] + w[0] * (R(0.5) * k.b[0] + twelfth * k.c[0]) + w[1] * (R(0.5) * k.b[1] + twelfth * k.c[1]) +
+        w[2] * (R(0.5) * k.b[2] + twelfth * k.c[2]);
+  der = w[0] * (k.b[0] + R(0.5) * k.c[0]) + w[1] * (k.b[1] + R(0.5) * k.c[1]) + w[2] * (k.b[2] + R(0.5) * k.c[2]);
 }
 
 // Normal sweep at face i+1/2 from c[0..5] = Q_{i-2..i+3}: left/right values and
