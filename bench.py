@@ -37,10 +37,50 @@ FLOPS_FLUX_PER_FACE = 30875.0
 # normal sweep plus first tangential sweep (2 Gauss lines) per face
 FLOPS_RECON_PER_FACE = 6630.0
 
+# HBM traffic of one flux-kernel launch at 256^3 from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, per dispatch), each divided by the ratio the
+# same counter reads for a device copy of known size (bench.py
+# --copy-calibration).  Valid only for the kernel sources it was measured on:
+# `traffic` is reported as null when their hash differs.
+TRAFFIC_MEASURED = None  # {"sources_sha256": ..., "fetch_bytes": ..., "write_bytes": ...}
+
 # MI355X published peaks
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("hgks.hip", "hgks_numerics.hpp"):
+        with open(os.path.join(ROOT, "paper_2207_01173_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n: int):
+    if TRAFFIC_MEASURED is None or n != TRAFFIC_MEASURED.get("n", 256):
+        return None
+    if TRAFFIC_MEASURED["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return TRAFFIC_MEASURED["fetch_bytes"] + TRAFFIC_MEASURED["write_bytes"]
+
+
+def copy_calibration(mib: int) -> int:
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (profile this run with rocprofv3 --pmc)."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
+    return 0
 
 
 def tgv_workload(n: int):
@@ -82,6 +122,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -96,6 +138,8 @@ def main() -> int:
     from paper_2207_01173_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     n = args.n
     p = tgv_workload(n)
     prec = hgks.FP64 if args.precision == "fp64" else hgks.MIXED
@@ -139,7 +183,7 @@ def main() -> int:
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": measured_traffic(n),
         "avg_launch_ms": round(flux_ms / flux_n, 4),
         "flops_per_face": FLOPS_FLUX_PER_FACE,
         "faces_per_launch": faces_per_launch,

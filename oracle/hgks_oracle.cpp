@@ -1357,6 +1357,17 @@ void hgo_residual(const hgo_config* cfg, const double* q, double dt, double* L, 
   build_grid(*cfg, g);
   residual(g, q, dt, L, dL);
 }
+/* Integrated flux F^n, dF^n/dt (global momentum frame) of face (f, a, b) of
+ * direction d: f the face index along d (face f between cells f-1 and f), a
+ * and b the cell indices along d+1 and d+2. */
+void hgo_face_flux(const hgo_config* cfg, const double* q, double dt, int d, int f, int a, int b, double out[10]) {
+  Grid g;
+  build_grid(*cfg, g);
+  std::vector<double> pad;
+  fill_padded(g, q, pad);
+  single_face_flux(g, pad, d, f, a, b, dt, out);
+}
+
 /* L, dL/dt at ncell cells ijk[3 * c + (0,1,2)]; outputs L[5 * c + comp]. */
 void hgo_residual_at(const hgo_config* cfg, const double* q, double dt, int ncell, const int* ijk, double* L,
                      double* dL) {

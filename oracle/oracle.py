@@ -103,6 +103,7 @@ def lib():
         L.hgo_normal_sweep.argtypes = [_D, _D]
         L.hgo_residual.argtypes = [P, _D, d, _D, _D]
         L.hgo_residual_at.argtypes = [P, _D, d, i, ctypes.POINTER(ctypes.c_int), _D, _D]
+        L.hgo_face_flux.argtypes = [P, _D, d, i, i, i, i, _D]
         L.hgo_cfl_dt.argtypes = [P, _D]
         L.hgo_cfl_dt.restype = d
         L.hgo_step.argtypes = [P, _D, i, d]
@@ -267,6 +268,15 @@ def residual_at(p: dict, q: np.ndarray, dt: float, cells):
     lib().hgo_residual_at(ctypes.byref(cfg), _ptr(q), float(dt), int(n),
                           ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(L), _ptr(dL))
     return L, dL
+
+
+def face_flux(p: dict, q: np.ndarray, dt: float, d: int, f: int, a: int, b: int):
+    """F^n and dF^n/dt (10 values) of one face of direction d."""
+    cfg = make_config(p)
+    q = _q(np.ascontiguousarray(q), cfg)
+    out = np.zeros(10)
+    lib().hgo_face_flux(ctypes.byref(cfg), _ptr(q), float(dt), int(d), int(f), int(a), int(b), _ptr(out))
+    return out
 
 
 def cfl_dt(p: dict, q: np.ndarray) -> float:

@@ -53,9 +53,30 @@ struct Scalars {
 
 __host__ __device__ inline size_t cells(const Params& P) { return (size_t)P.n[0] * P.n[1] * P.n[2]; }
 
-// Face extents of direction d: one more face than cells along d.
+// Face extents of direction d: one more face than cells along d (on a
+// periodic axis the last face repeats face 0 and is computed from the same
+// data).
 __host__ __device__ inline void face_extents(const Params& P, int d, int fe[3]) {
   for (int a = 0; a < 3; ++a) fe[a] = P.n[a] + (a == d ? 1 : 0);
+}
+
+// Tile order across the grid of blocks: tile index `fast` varies fastest
+// (neighbouring tiles along that axis share stencil data), and the blocks are
+// remapped so that each of the 8 XCDs (which take blocks round robin and have
+// their own L2) works through a contiguous run of tiles.
+__device__ __forceinline__ int xcd_linear_block(int nblocks) {
+  const int bid = blockIdx.x;
+  const int full = (nblocks / 8) * 8;
+  if (bid >= full) return bid;
+  return (bid % 8) * (full / 8) + bid / 8;
+}
+__device__ __forceinline__ void tile_coords(int lin, const int nt[3], int fast, int t[3]) {
+  const int a1 = fast == 0 ? 1 : 0;
+  const int a2 = fast == 2 ? 1 : 2;
+  t[fast] = lin % nt[fast];
+  lin /= nt[fast];
+  t[a1] = lin % nt[a1];
+  t[a2] = lin / nt[a1];
 }
 // Extents of buffer B of direction d: faces, plus two ghost rows on each side
 // of t2 when t2 is a wall axis (the second tangential sweep reads them).
@@ -137,12 +158,12 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   SA[D1] += 4;
   int be[3], bo[3];
   b_extents(P, DIR, be, bo);
-  const int nt0 = (be[0] + S[0] - 1) / S[0], nt1 = (be[1] + S[1] - 1) / S[1];
-  const int bid = blockIdx.x;
-  int org[3];
-  org[0] = (bid % nt0) * S[0] + bo[0];
-  org[1] = ((bid / nt0) % nt1) * S[1] + bo[1];
-  org[2] = (bid / (nt0 * nt1)) * S[2] + bo[2];
+  int nt[3], tc[3], org[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) nt[a] = (be[a] + S[a] - 1) / S[a];
+  tile_coords(xcd_linear_block(nt[0] * nt[1] * nt[2]), nt, DIR, tc);  // normal tiles adjacent
+#pragma unroll
+  for (int a = 0; a < 3; ++a) org[a] = tc[a] * S[a] + bo[a];
 
   // reference state subtracted before the reconstruction (zero on the FP64 path)
   double ref[5];
@@ -164,7 +185,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
     int f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) f[a] = org[a] + l[a] - (a == D1 ? 2 : 0);
-    bool ok = f[DIR] <= P.n[DIR] && f[D2] < bo[D2] + be[D2] && f[D1] >= -2 && f[D1] < P.n[D1] + 2;
+    bool ok = f[DIR] < be[DIR] && f[D2] < bo[D2] + be[D2] && f[D1] >= -2 && f[D1] < P.n[D1] + 2;
     if (!ok) continue;
     R c[6][5];
 #pragma unroll
@@ -202,7 +223,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   int f[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = org[a] + lo[a];
-  if (f[DIR] > P.n[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;
+  if (f[DIR] >= be[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;
   int ai[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
@@ -254,13 +275,14 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
   int fe[3], be[3], bo[3];
   face_extents(P, DIR, fe);
   b_extents(P, DIR, be, bo);
-  const int nt0 = (fe[0] + 15) / 16, nt1 = (fe[1] + 3) / 4;
-  const int bid = blockIdx.x;
+  const int nt[3] = {(fe[0] + 15) / 16, (fe[1] + 3) / 4, fe[2]};
+  int tc[3];
+  tile_coords(xcd_linear_block(nt[0] * nt[1] * nt[2]), nt, D2, tc);  // t2 tiles adjacent
   const int tid = threadIdx.x;
   int f[3];
-  f[0] = (bid % nt0) * 16 + (tid & 15);
-  f[1] = ((bid / nt0) % nt1) * 4 + (tid >> 6);
-  f[2] = bid / (nt0 * nt1);
+  f[0] = tc[0] * 16 + (tid & 15);
+  f[1] = tc[1] * 4 + (tid >> 6);
+  f[2] = tc[2];
   const int gpi = (tid >> 4) & 3;
   const int g1 = gpi >> 1, g2 = gpi & 1;
   const bool valid = f[0] < fe[0] && f[1] < fe[1] && f[2] < fe[2];
@@ -632,19 +654,35 @@ __global__ __launch_bounds__(CELL_THREADS) void stats_partial_kernel(const doubl
   if (threadIdx.x < ST_COUNT) part[(size_t)blockIdx.x * ST_COUNT + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Deterministic final reduction: thread m reduces field m over all blocks in order.
-__global__ void stats_final_kernel(const double* __restrict__ part, int nblocks, double* __restrict__ out) {
-  const int m = threadIdx.x;
-  if (m >= ST_COUNT) return;
-  double a = part[m];
-  for (int b = 1; b < nblocks; ++b) {
-    double x = part[(size_t)b * ST_COUNT + m];
-    if (m >= ST_MAX && m < ST_MAX + 5) a = fmax(a, x);
-    else if (m == ST_MINP || m == ST_MINR) a = fmin(a, x);
-    else if (m == ST_BAD) a = fmax(a, x);
-    else a += x;
+// Deterministic final reduction: block m reduces field m; thread t combines
+// blocks t, t + 256, ... in order, then a fixed tree combines the threads.
+__global__ __launch_bounds__(256) void stats_final_kernel(const double* __restrict__ part, int nblocks,
+                                                          double* __restrict__ out) {
+  __shared__ double red[256];
+  const int m = blockIdx.x, t = threadIdx.x;
+  const bool is_max = (m >= ST_MAX && m < ST_MAX + 5) || m == ST_BAD;
+  const bool is_min = m == ST_MINP || m == ST_MINR;
+  double a = is_min ? INFINITY : (is_max ? -INFINITY : 0.0);
+  for (int b = t; b < nblocks; b += 256) {
+    const double x = part[(size_t)b * ST_COUNT + m];
+    a = is_max ? fmax(a, x) : (is_min ? fmin(a, x) : a + x);
   }
-  out[m] = a;
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      const double x = red[t + w], y = red[t];
+      red[t] = is_max ? fmax(y, x) : (is_min ? fmin(y, x) : y + x);
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[m] = red[0];
+}
+
+// Reference state of the mixed path: the volume mean of Q, from the totals of
+// the statistics reduction.  Reconstruction works on deviations from it.
+__global__ void mean_state_kernel(const double* __restrict__ fin, double inv_vol, double* __restrict__ qref) {
+  if (threadIdx.x < 5) qref[threadIdx.x] = fin[ST_TOT + threadIdx.x] * inv_vol;
 }
 
 }  // namespace hgks
@@ -938,6 +976,15 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   HIP_TRY(ctx, hipMemcpyAsync(ctx->qref, qref, sizeof(qref), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   hipLaunchKernelGGL(wave_rate_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->sc);
+  if (precision_mixed(*cfg)) {
+    const int nb = ctx->L.stat_blocks;
+    double* fin = ctx->part + (size_t)nb * ST_COUNT;
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= cfg->hi[a] - cfg->lo[a];
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(nb), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->part);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(ST_COUNT), dim3(256), 0, ctx->stream, ctx->part, nb, fin);
+    hipLaunchKernelGGL(mean_state_kernel, dim3(1), dim3(64), 0, ctx->stream, fin, 1.0 / vol, ctx->qref);
+  }
   HIP_TRY(ctx, hipGetLastError());
   *out = ctx;
   return HGKS_OK;
@@ -974,7 +1021,7 @@ hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out) {
   const int nb = ctx->L.stat_blocks;
   double* fin = ctx->part + (size_t)nb * ST_COUNT;
   hipLaunchKernelGGL(stats_partial_kernel, dim3(nb), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->part);
-  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->part, nb, fin);
+  hipLaunchKernelGGL(stats_final_kernel, dim3(ST_COUNT), dim3(256), 0, ctx->stream, ctx->part, nb, fin);
   HIP_TRY(ctx, hipGetLastError());
   double h[ST_COUNT];
   Scalars sc;

@@ -1,0 +1,122 @@
+"""GPU tests of the mixed-precision path (FP32 reconstruction and flux on
+deviations from an FP64 reference state, FP64 state and update) and of the
+channel configuration (isothermal walls on y, tanh-stretched y, power-law
+viscosity, constant body force), through the C ABI, against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2207_01173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_01173_amd import hgks
+
+    hgks.lib()
+    return hgks
+
+
+def rel_err(got, ref):
+    axes = tuple(range(1, ref.ndim))
+    return np.abs(got - ref).max(axis=axes) / np.abs(ref).max(axis=axes)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("ma", [0.1, 0.29])
+def test_mixed_precision_error_is_small_and_stated(hg, oracle, ma):
+    """Mixed path vs the FP64 oracle after 10 steps of the 32^3 TGV: the
+    state error (relative max-norm per component) is reported and bounded;
+    the FP64 path on the same case sits at rounding level."""
+    p = W.tgv_params(32, ma=ma, re=1600.0, pr=0.72, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    dt = oracle.cfl_dt(p, q0)
+    ref, _ = oracle.step(p, q0, 10, dt)
+    s = hg.Solver(p, q0, precision=hg.MIXED)
+    s.step(10, dt)
+    got = s.state()
+    st = s.stats()
+    s.close()
+    err = rel_err(got, ref)
+    so = oracle.stats(p, ref)
+    eEk = abs(st["Ek"] - so["Ek"]) / so["Ek"]
+    eeps = abs(st["eps_com"] - so["eps_com"]) / so["eps_com"]
+    say(f"mixed TGV32 Ma={ma}: state rel err {err}, E_k rel err {eEk:.2e}, eps_com rel err {eeps:.2e}")
+    assert np.isfinite(got).all()
+    assert (err <= 1e-4).all(), err
+    assert eEk <= 1e-5 and eeps <= 1e-3
+
+
+def test_mixed_uniform_flow_preserved(hg):
+    n = (12, 10, 8)
+    p = W.tgv_params(n, ma=0.3, re=100.0)
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.3), f(0.3), f(-0.2), f(0.1), f(2.0)))
+    s = hg.Solver(p, q0, precision=hg.MIXED)
+    s.step(3, 0.01)
+    # the flux of a uniform state is identical on every face: the update cancels exactly
+    np.testing.assert_array_equal(s.state(), q0)
+    s.close()
+
+
+def channel_case(n):
+    p = W.channel_params(n, ma_b=0.5, re_b=3000.0)
+    q = W.channel_initial(p, seed=2207)
+    return p, q
+
+
+@pytest.mark.parametrize("n", [(16, 24, 12), (20, 16, 8)])
+def test_channel_residual_parity(hg, oracle, n):
+    """Walls on y (mirror ghosts), stretched y, power-law mu, body force."""
+    p, q = channel_case(n)
+    dt = 0.5 * oracle.cfl_dt(p, q)
+    say("channel residual", n, "dt", dt)
+    s = hg.Solver(p, q)
+    L, dL = s.residual(q, dt)
+    L, dL = L.cpu().numpy(), dL.cpu().numpy()
+    s.close()
+    Lo, dLo = oracle.residual(p, q, dt)
+    eL, edL = rel_err(L, Lo), rel_err(dL, dLo)
+    say("  L err", eL, "dL err", edL)
+    assert (eL <= 1e-11).all() and (edL <= 1e-10).all()
+
+
+def test_channel_steps_parity(hg, oracle):
+    """Five CFL steps of a small stretched-wall channel: FP64 path vs oracle."""
+    p, q = channel_case((16, 24, 12))
+    s = hg.Solver(p, q)
+    s.step(5, 0.0)
+    got = s.state()
+    dt_gpu = s.stats()["dt_last"]
+    s.close()
+    ref, dt_last = oracle.step(p, q, 5, 0.0)
+    err = rel_err(got, ref)
+    say("channel 5 steps err", err, "dt", dt_gpu, dt_last)
+    assert (err <= 1e-11).all()
+    assert abs(dt_gpu - dt_last) <= 1e-12 * dt_last
+
+
+def test_channel_wall_at_rest_stays_at_rest(hg):
+    """Fluid at rest at the wall temperature with no force: the mirror ghosts
+    reproduce the interior, every flux is the uniform pressure flux, nothing
+    moves (to rounding)."""
+    p = W.channel_params((8, 16, 8), ma_b=0.5, re_b=3000.0, force=0.0)
+    nx, ny, nz = p["n"]
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.0), f(0.0), f(0.0), f(0.0), f(p["T_wall"])))
+    s = hg.Solver(p, q0)
+    s.step(3, 1e-3)
+    got = s.state()
+    s.close()
+    assert np.abs(got - q0).max() <= 1e-12 * np.abs(q0).max()

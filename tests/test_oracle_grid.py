@@ -167,3 +167,63 @@ def test_residual_at_matches_full_residual(oracle):
     for c, (i, j, k) in enumerate(cells):
         np.testing.assert_array_equal(La[c], L[:, k, j, i])
         np.testing.assert_array_equal(dLa[c], dL[:, k, j, i])
+
+
+def test_channel_rest_state_oracle(oracle):
+    """Fluid at rest at the wall temperature, no force: mirror ghosts equal the
+    interior (T_g = 2 T_w - T = T_w), so nothing moves."""
+    p = W.channel_params((8, 12, 6), force=0.0)
+    nx, ny, nz = p["n"]
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.0), f(0.0), f(0.0), f(0.0), f(p["T_wall"])))
+    q2, _ = oracle.step(p, q0, 2, 1e-3)
+    assert np.abs(q2 - q0).max() <= 1e-13 * np.abs(q0).max()
+
+
+def test_channel_y_reflection_equivariance(oracle):
+    """The stretched channel is symmetric about y = 0: reflecting y (cells
+    reversed, V negated) commutes with a step.  Pins the wall mirror on both
+    walls and the symmetry of the tanh metrics."""
+    p = W.channel_params((8, 12, 6))
+    q = W.channel_initial(p, seed=5)
+
+    def refl(a):
+        m = np.ascontiguousarray(a[:, :, ::-1, :])
+        m[2] *= -1
+        return m
+
+    a, _ = oracle.step(p, q, 2, 2e-3)
+    b, _ = oracle.step(p, refl(q), 2, 2e-3)
+    err = np.abs(b - refl(a)).max(axis=(1, 2, 3)) / np.abs(a).max(axis=(1, 2, 3))
+    assert (err <= 1e-13).all(), err
+
+
+def test_channel_poiseuille_force_balance(oracle):
+    """Laminar Poiseuille profile U = U0 (1 - y^2) at uniform temperature with
+    the body force f = 2 nu U0 that balances it: the streamwise momentum
+    residual vanishes up to the discretisation error in the interior.  Next
+    to the walls the mirror ghosts (R17) extend the parabola as an odd
+    function whose curvature flips sign at the wall; slopes from symmetric
+    stencils on that extension are off by O(h U''), so the wall shear stress
+    is off by O(mu U'' h) and the first cell's residual by O(mu U'') = O(f):
+    a property of the mirror wall, bounded here, not a defect."""
+    p = W.channel_params((6, 32, 6), ma_b=0.3, re_b=500.0, y_stretch=1.5)
+    rho0, U0 = 1.0, 1.0
+    nu = p["mu_ref"] / rho0
+    fx = 2.0 * nu * U0
+    p["body_force"] = (fx, 0.0, 0.0)
+    nx, ny, nz = p["n"]
+    y = W.channel_y_centres(p)
+    U = np.broadcast_to((U0 * (1.0 - y * y))[None, :, None], (nz, ny, nx))
+    z = np.zeros((nz, ny, nx))
+    q = np.ascontiguousarray(W.conserved(z + rho0, U, z, z, z + rho0 * p["T_wall"]))
+    L, _ = oracle.residual(p, q, 1e-3)
+    lx = np.abs(L[1]).max(axis=(0, 2))  # per y row
+    interior = lx[4:-4].max()
+    print("Poiseuille residual/force interior", interior / fx, "wall rows", lx[:3] / fx)
+    assert interior <= 0.02 * fx
+    assert lx[3:-3].max() <= 0.3 * fx and lx.max() <= 5.0 * fx
+    # without the force the profile decays: the residual is the viscous term -rho f
+    p["body_force"] = (0.0, 0.0, 0.0)
+    L0, _ = oracle.residual(p, q, 1e-3)
+    np.testing.assert_allclose(L0[1][:, 8:-8, :], -rho0 * fx, rtol=0.02)
