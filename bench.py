@@ -83,6 +83,53 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def ensemble_bench(steps: int, precision: str) -> dict:
+    """64 TGV instances, N from {24, 32, 48, 64, 96}, Ma ~ U[0.1, 0.5], Re ~
+    U[400, 3000] (seeded): one batched context (persistent tile launches,
+    replayed graph, autotuned shapes) against a loop over per-instance
+    contexts, both advancing every instance `steps` CFL steps."""
+    import torch
+
+    from paper_2207_01173_amd import hgks
+    from paper_2207_01173_amd import workloads as W
+
+    prec = hgks.FP64 if precision == "fp64" else hgks.MIXED
+    params = W.tgv_ensemble(64)
+    q0 = [W.tgv_initial(p) for p in params]
+    cells = sum(p["n"][0] * p["n"][1] * p["n"][2] for p in params)
+    print(f"# ensemble: {len(params)} instances, {cells} cells", file=sys.stderr, flush=True)
+    b = hgks.Batch(params, q0, precision=prec)
+    info = b.info()
+    b.step(1)
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    print(f"# batched: {tb:.3f} s; per-instance loop next", file=sys.stderr, flush=True)
+    solvers = [hgks.Solver(p, q, precision=prec) for p, q in zip(params, q0)]
+    for s in solvers:
+        s.step(1, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s in solvers:
+            s.step(1, 0.0)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    cs = 2.0 * cells * steps
+    return {
+        "metric": "cell-stage updates/s, 64-instance TGV ensemble (N in {24..96}, Ma 0.1-0.5, Re 400-3000)",
+        "unit": UNIT, "steps": steps, "precision": precision, "instances": len(params), "cells": cells,
+        "batched": {"value": cs / tb, "seconds": tb, "launch_shapes": info},
+        "per_instance_loop": {"value": cs / tl, "seconds": tl},
+        "speedup": tl / tb,
+    }
+
+
 def tgv_workload(n: int):
     from paper_2207_01173_amd import workloads as W
 
@@ -122,6 +169,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--ensemble", action="store_true",
+                    help="measure the 64-instance ensemble (batched vs per-instance loop) instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -140,6 +189,9 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.ensemble:
+        print(json.dumps(ensemble_bench(args.steps, args.precision)), flush=True)
+        return 0
     n = args.n
     p = tgv_workload(n)
     prec = hgks.FP64 if args.precision == "fp64" else hgks.MIXED

@@ -133,6 +133,29 @@ hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* 
 hgks_status hgks_profile(hgks_ctx ctx, int32_t enable);
 hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int64_t launches[HGKS_PROFILE_CLASSES]);
 
+/* ---- Batched ensemble ----------------------------------------------------
+ * Many independent instances (each its own grid size, gas and state) advanced
+ * together: every kernel of a step is one launch over the tiles of all
+ * instances (a persistent grid striding a tile table), each S2O4 step is
+ * captured once in a HIP graph and replayed, and each instance takes its own
+ * CFL time step.  Instance i's state q_devs[i] has the single-instance layout.
+ * For the callers running many small problems in one stream (ensembles,
+ * parameter sweeps).  Errors: HGKS_E_INVALID for any invalid member config
+ * (its index is reported by hgks_last_error), HGKS_E_DEVICE. */
+hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes);
+hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev,
+                            size_t ws_bytes, void* hip_stream, hgks_ctx* out);
+/* Advance every instance nsteps steps with its own CFL time step (graph
+ * replays; asynchronous). */
+hgks_status hgks_batch_step(hgks_ctx ctx, int32_t nsteps);
+/* Statistics of instance i (synchronises the stream). */
+hgks_status hgks_batch_stats(hgks_ctx ctx, int32_t i, hgks_stats_t* out);
+/* Launch shapes chosen by the autotuner: info = {instances, flux tile width
+ * (faces along x), reconstruction grid, flux grid, update grid, source (1
+ * tuned now, 2 read from the file named by HGKS_TUNE_CACHE), reconstruction
+ * tiles per step (3 directions), cell blocks}. */
+hgks_status hgks_batch_info(hgks_ctx ctx, int64_t info[8]);
+
 /* Release the host context (device memory stays the caller's). */
 hgks_status hgks_destroy(hgks_ctx ctx);
 

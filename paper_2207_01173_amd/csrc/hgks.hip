@@ -12,7 +12,9 @@
 // the new state for the next CFL time step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -128,9 +130,9 @@ __device__ __forceinline__ void load_cell(const double* __restrict__ q, const Pa
 }
 
 template <int DIR> struct ReconTile;  // faces per tile in the local frame (n, t1, t2)
-template <> struct ReconTile<0> { static constexpr int TN = 16, T1 = 4, T2 = 1; };
-template <> struct ReconTile<1> { static constexpr int TN = 1, T1 = 4, T2 = 16; };
-template <> struct ReconTile<2> { static constexpr int TN = 1, T1 = 16, T2 = 4; };
+template <> struct ReconTile<0> { static constexpr int TN = 16, T1 = 8, T2 = 1; };
+template <> struct ReconTile<1> { static constexpr int TN = 1, T1 = 8, T2 = 16; };
+template <> struct ReconTile<2> { static constexpr int TN = 1, T1 = 16, T2 = 8; };
 
 template <int DIR> __host__ __device__ inline void recon_tile_extents(int S[3]) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
@@ -139,18 +141,29 @@ template <int DIR> __host__ __device__ inline void recon_tile_extents(int S[3]) 
   S[D2] = ReconTile<DIR>::T2;
 }
 
-constexpr int RECON_THREADS = 128;
+constexpr int RECON_THREADS = 256;
 
 // Normal sweep and first tangential sweep for a tile of faces of direction DIR.
 // LDS holds the 25 normal-sweep quantities of the tile plus a 2-face halo along
 // t1.  Output B[(q * 2 + g1) * NB + face] in the arithmetic type R.
+template <int DIR> constexpr int recon_lds_faces() {
+  return ReconTile<DIR>::TN * (ReconTile<DIR>::T1 + 4) * ReconTile<DIR>::T2;
+}
+
+// Number of reconstruction tiles of direction DIR.
+template <int DIR> __host__ __device__ inline int recon_tiles(const Params& P) {
+  int S[3], be[3], bo[3];
+  recon_tile_extents<DIR>(S);
+  b_extents(P, DIR, be, bo);
+  return ((be[0] + S[0] - 1) / S[0]) * ((be[1] + S[1] - 1) / S[1]) * ((be[2] + S[2] - 1) / S[2]);
+}
+
 template <int DIR, class R>
-__global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __restrict__ q, Params P,
-                                                              const double* __restrict__ qref,
-                                                              R* __restrict__ B) {
+__device__ __forceinline__ void recon_tile(const double* __restrict__ q, const Params& P,
+                                           const double* __restrict__ qref, R* __restrict__ B, int lin,
+                                           R (*A)[recon_lds_faces<DIR>()]) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
-  constexpr int NA = ReconTile<DIR>::TN * (ReconTile<DIR>::T1 + 4) * ReconTile<DIR>::T2;
-  __shared__ R A[25][NA];
+  constexpr int NA = recon_lds_faces<DIR>();
 
   int S[3];
   recon_tile_extents<DIR>(S);
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   int nt[3], tc[3], org[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) nt[a] = (be[a] + S[a] - 1) / S[a];
-  tile_coords(xcd_linear_block(nt[0] * nt[1] * nt[2]), nt, DIR, tc);  // normal tiles adjacent
+  tile_coords(lin, nt, DIR, tc);  // normal tiles adjacent
 #pragma unroll
   for (int a = 0; a < 3; ++a) org[a] = tc[a] * S[a] + bo[a];
 
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   __syncthreads();
 
   // ---- first tangential sweep: one (face, Gauss line) per thread --------
-  const int o = threadIdx.x & 63, g1 = threadIdx.x >> 6;
+  const int o = threadIdx.x & 127, g1 = threadIdx.x >> 7;
   int lo[3];
   lo[0] = o % S[0];
   lo[1] = (o / S[0]) % S[1];
@@ -223,7 +236,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   int f[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = org[a] + lo[a];
-  if (f[DIR] >= be[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;
+  if (f[DIR] >= be[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;  // this thread only
   int ai[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
@@ -261,27 +274,50 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
   }
 }
 
+template <int DIR, class R>
+__global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __restrict__ q, Params P,
+                                                              const double* __restrict__ qref,
+                                                              R* __restrict__ B) {
+  __shared__ R A[25][recon_lds_faces<DIR>()];
+  recon_tile<DIR, R>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR>(P)), A);
+}
+
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
 
-// Second tangential sweep, Gauss-point flux, Gauss sum, F^n and dF^n/dt.
-// Lane layout in a wavefront: lanes 16 g .. 16 g + 15 hold Gauss point g of
-// 16 consecutive faces along x; the four waves of the block take four rows.
-template <int DIR, class R>
-__global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict__ B, Params P,
-                                                            const double* __restrict__ qref,
-                                                            const Scalars* __restrict__ sc, int use_residual_dt,
-                                                            double* __restrict__ F) {
+// Flux tiles: 64 faces, TX along x times 64/TX along y, one z plane.
+template <int TX> __host__ __device__ inline void flux_tile_counts(const Params& P, int d, int nt[3]) {
+  int fe[3];
+  face_extents(P, d, fe);
+  nt[0] = (fe[0] + TX - 1) / TX;
+  nt[1] = (fe[1] + 64 / TX - 1) / (64 / TX);
+  nt[2] = fe[2];
+}
+template <int TX> __host__ __device__ inline int flux_tiles(const Params& P, int d) {
+  int nt[3];
+  flux_tile_counts<TX>(P, d, nt);
+  return nt[0] * nt[1] * nt[2];
+}
+
+// Second tangential sweep, Gauss-point flux, Gauss sum, F^n and dF^n/dt for
+// flux tile `lin` of direction DIR.  Lane layout in a wavefront: lanes
+// 16 g .. 16 g + 15 hold Gauss point g of 16 consecutive faces along x; the
+// four waves of the block take four 16-face groups of the TX x (64/TX) tile.
+template <int DIR, class R, int TX>
+__device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params& P, const double* __restrict__ qref,
+                                          double dt, double* __restrict__ F, int lin) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  constexpr int GX = TX / 16;  // 16-face groups along x per tile row
   int fe[3], be[3], bo[3];
   face_extents(P, DIR, fe);
   b_extents(P, DIR, be, bo);
-  const int nt[3] = {(fe[0] + 15) / 16, (fe[1] + 3) / 4, fe[2]};
-  int tc[3];
-  tile_coords(xcd_linear_block(nt[0] * nt[1] * nt[2]), nt, D2, tc);  // t2 tiles adjacent
+  int nt[3], tc[3];
+  flux_tile_counts<TX>(P, DIR, nt);
+  tile_coords(lin, nt, D2, tc);  // t2 tiles adjacent
   const int tid = threadIdx.x;
+  const int w = tid >> 6;
   int f[3];
-  f[0] = tc[0] * 16 + (tid & 15);
-  f[1] = tc[1] * 4 + (tid >> 6);
+  f[0] = tc[0] * TX + (w % GX) * 16 + (tid & 15);
+  f[1] = tc[1] * (64 / TX) + w / GX;
   f[2] = tc[2];
   const int gpi = (tid >> 4) & 3;
   const int g1 = gpi >> 1, g2 = gpi & 1;
@@ -290,7 +326,6 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
     f[0] = min(f[0], fe[0] - 1);
     f[1] = min(f[1], fe[1] - 1);
   }
-  const double dt = use_residual_dt ? sc->dt_residual : sc->dt;
 
   // ---- second tangential sweep along t2 ----------------------------------
   const size_t NB = (size_t)be[0] * be[1] * be[2];
@@ -401,7 +436,7 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
     s1[k] += __shfl_xor(s1[k], 32);
     s2[k] += __shfl_xor(s2[k], 32);
   }
-  if (!valid || gpi != 0) return;
+  if (!valid || gpi != 0) return;  // this lane only
   const double area = P.hcell[D1][f[D1]] * P.hcell[D2][f[D2]];
   double loc[10];
 #pragma unroll
@@ -420,6 +455,15 @@ __global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict_
     F[gcomp[k] * NF + fi] = loc[k];
     F[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
   }
+}
+
+template <int DIR, class R>
+__global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict__ B, Params P,
+                                                            const double* __restrict__ qref,
+                                                            const Scalars* __restrict__ sc, int use_residual_dt,
+                                                            double* __restrict__ F) {
+  const double dt = use_residual_dt ? sc->dt_residual : sc->dt;
+  flux_tile<DIR, R, 16>(B, P, qref, dt, F, xcd_linear_block(flux_tiles<16>(P, DIR)));
 }
 
 // L and dL/dt of one cell from the six face fluxes, plus the body-force source
@@ -484,18 +528,19 @@ __device__ __forceinline__ void block_max_atomic(double r, unsigned long long* d
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
     atomicMax(dst, (unsigned long long)__double_as_longlong(m));
   }
+  __syncthreads();  // red[] may be reused by the next call in this block
 }
 
 constexpr int CELL_THREADS = 256;
 
+// S2O4 stage for cell block `blk` (CELL_THREADS cells) of one instance.
 template <int STAGE>
-__global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict__ q, double* __restrict__ qs,
-                                                              double* __restrict__ acc, const double* __restrict__ F0,
-                                                              const double* __restrict__ F1,
-                                                              const double* __restrict__ F2, Params P,
-                                                              Scalars* __restrict__ sc) {
+__device__ __forceinline__ void update_block(double* __restrict__ q, double* __restrict__ qs, double* __restrict__ acc,
+                                             const double* __restrict__ F0, const double* __restrict__ F1,
+                                             const double* __restrict__ F2, const Params& P, Scalars* __restrict__ sc,
+                                             size_t blk) {
   const size_t n3 = cells(P);
-  const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  const size_t c = blk * CELL_THREADS + threadIdx.x;
   double rate = 0.0;
   if (c < n3) {
     const int i = (int)(c % P.n[0]);
@@ -523,6 +568,15 @@ __global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict
     }
   }
   if (STAGE == 2) block_max_atomic(rate, &sc->smax);
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict__ q, double* __restrict__ qs,
+                                                              double* __restrict__ acc, const double* __restrict__ F0,
+                                                              const double* __restrict__ F1,
+                                                              const double* __restrict__ F2, Params P,
+                                                              Scalars* __restrict__ sc) {
+  update_block<STAGE>(q, qs, acc, F0, F1, F2, P, sc, blockIdx.x);
 }
 
 __global__ __launch_bounds__(CELL_THREADS) void residual_kernel(const double* __restrict__ qe,
@@ -679,6 +733,107 @@ __global__ __launch_bounds__(256) void stats_final_kernel(const double* __restri
   if (t == 0) out[m] = red[0];
 }
 
+// ---- batched ensemble ------------------------------------------------------
+// Each instance has its own parameters, state, workspace and device scalars.
+// Work lists (tiles or cell blocks) of all instances are concatenated; row r
+// of the prefix table holds the instance offsets of list r.
+struct BatchEntry {
+  Params P;
+  double* q;
+  double* qs;
+  double* acc;
+  void* B;
+  double* F[3];
+  Scalars* sc;
+  double* qref;
+  double cfl;
+};
+enum { PRE_RECON = 0, PRE_FLUX = 3, PRE_CELL = 12, PRE_ROWS = 13 };  // flux rows: TX 16, 32, 64 x 3 directions
+template <int TX> constexpr int flux_row(int d) { return PRE_FLUX + 3 * (TX == 16 ? 0 : (TX == 32 ? 1 : 2)) + d; }
+
+struct BatchTable {
+  const BatchEntry* E;
+  const int* pre;  // [PRE_ROWS][n + 1]
+  int n;
+};
+
+__device__ __forceinline__ int find_instance(const int* pre, int n, int t) {
+  int lo = 0, hi = n;  // pre[lo] <= t < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Contiguous chunk [t0, t1) of a work list of `total` items for this block of
+// a persistent grid; blocks are XCD-remapped so neighbouring chunks share an L2.
+__device__ __forceinline__ void block_chunk(int total, int& t0, int& t1) {
+  const int G = gridDim.x;
+  const int lb = xcd_linear_block(G);
+  const int chunk = (total + G - 1) / G;
+  t0 = min(total, lb * chunk);
+  t1 = min(total, t0 + chunk);
+}
+
+template <int DIR, class R>
+__global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T, int src_qs) {
+  __shared__ R A[25][recon_lds_faces<DIR>()];
+  const int* pre = T.pre + (PRE_RECON + DIR) * (T.n + 1);
+  int t0, t1;
+  block_chunk(pre[T.n], t0, t1);
+  if (t0 >= t1) return;
+  int inst = find_instance(pre, T.n, t0);
+  for (int t = t0; t < t1; ++t) {
+    while (t >= pre[inst + 1]) ++inst;
+    const BatchEntry& e = T.E[inst];
+    __syncthreads();  // the previous tile's reads of A are complete
+    recon_tile<DIR, R>(src_qs ? e.qs : e.q, e.P, e.qref, static_cast<R*>(e.B), t - pre[inst], A);
+  }
+}
+
+template <int DIR, class R, int TX>
+__global__ __launch_bounds__(FLUX_THREADS) void flux_batch_kernel(BatchTable T) {
+  const int* pre = T.pre + flux_row<TX>(DIR) * (T.n + 1);
+  int t0, t1;
+  block_chunk(pre[T.n], t0, t1);
+  if (t0 >= t1) return;
+  int inst = find_instance(pre, T.n, t0);
+  for (int t = t0; t < t1; ++t) {
+    while (t >= pre[inst + 1]) ++inst;
+    const BatchEntry& e = T.E[inst];
+    flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, e.sc->dt, e.F[DIR], t - pre[inst]);
+  }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T) {
+  const int* pre = T.pre + PRE_CELL * (T.n + 1);
+  int t0, t1;
+  block_chunk(pre[T.n], t0, t1);
+  if (t0 >= t1) return;
+  int inst = find_instance(pre, T.n, t0);
+  for (int t = t0; t < t1; ++t) {
+    while (t >= pre[inst + 1]) ++inst;
+    const BatchEntry& e = T.E[inst];
+    update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, (size_t)(t - pre[inst]));
+  }
+}
+
+// Start of a batched step: each instance takes its own CFL time step.
+__global__ void begin_step_batch_kernel(BatchTable T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T.n) return;
+  Scalars* sc = T.E[i].sc;
+  const double smax = __longlong_as_double((long long)sc->smax);
+  const double dt = T.E[i].cfl / smax;
+  sc->dt = dt;
+  sc->t += dt;
+  sc->steps += 1.0;
+  sc->smax = 0ull;
+}
+
 // Reference state of the mixed path: the volume mean of Q, from the totals of
 // the statistics reduction.  Reconstruction works on deviations from it.
 __global__ void mean_state_kernel(const double* __restrict__ fin, double inv_vol, double* __restrict__ qref) {
@@ -789,6 +944,14 @@ struct hgks_ctx_s {
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_class;
   size_t ev_used = 0;
+  // batched ensemble (hgks_batch_init): member contexts, device work table,
+  // tuned launch shapes and the captured step
+  std::vector<hgks_ctx> members;
+  BatchTable table{};
+  int total_recon[3] = {0, 0, 0}, total_flux[3][3] = {{0}}, total_cells = 0;
+  int tx = 16, g_recon = 0, g_flux = 0, g_update = 0, tune_source = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 enum { PROF_RECON = 0, PROF_FLUX = 1, PROF_UPDATE = 2, PROF_OTHER = 3 };
@@ -853,21 +1016,13 @@ static hgks_status launch_fluxes(hgks_ctx ctx, const double* qin, int use_residu
   const Params& P = ctx->P;
   R* B = static_cast<R*>(ctx->B);
   const double* qref = ctx->qref;
-  auto recon_blocks = [&](int d, int S0, int S1, int S2) {
-    int be[3], bo[3];
-    b_extents(P, d, be, bo);
-    return (unsigned)(((be[0] + S0 - 1) / S0) * ((be[1] + S1 - 1) / S1) * ((be[2] + S2 - 1) / S2));
+  auto recon_blocks = [&](int d) {
+    return (unsigned)(d == 0 ? recon_tiles<0>(P) : (d == 1 ? recon_tiles<1>(P) : recon_tiles<2>(P)));
   };
-  auto flux_blocks = [&](int d) {
-    int fe[3];
-    face_extents(P, d, fe);
-    return (unsigned)(((fe[0] + 15) / 16) * ((fe[1] + 3) / 4) * fe[2]);
-  };
-  int S[3];
+  auto flux_blocks = [&](int d) { return (unsigned)flux_tiles<16>(P, d); };
 #define HGKS_DIRECTION(D)                                                                                    \
-  recon_tile_extents<D>(S);                                                                                  \
   HIP_TRY(ctx, prof_begin(ctx, PROF_RECON));                                                                 \
-  hipLaunchKernelGGL((recon_kernel<D, R>), dim3(recon_blocks(D, S[0], S[1], S[2])), dim3(RECON_THREADS), 0,  \
+  hipLaunchKernelGGL((recon_kernel<D, R>), dim3(recon_blocks(D)), dim3(RECON_THREADS), 0,                    \
                      ctx->stream, qin, P, qref, B);                                                          \
   HIP_TRY(ctx, prof_end(ctx));                                                                               \
   HIP_TRY(ctx, prof_begin(ctx, PROF_FLUX));                                                                  \
@@ -888,6 +1043,162 @@ static hgks_status launch_fluxes_any(hgks_ctx ctx, const double* qin, int use_re
 }
 
 static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CELL_THREADS - 1) / CELL_THREADS); }
+
+// ---- batched ensemble: host side ------------------------------------------
+
+static size_t batch_table_bytes(int n) {
+  return align256((size_t)n * sizeof(BatchEntry)) + align256((size_t)PRE_ROWS * (n + 1) * sizeof(int));
+}
+
+template <class R, int TX>
+static void enqueue_batch_fluxes_tx(hgks_ctx b, int src_qs) {
+  const BatchTable T = b->table;
+  hipLaunchKernelGGL((recon_batch_kernel<0, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
+  hipLaunchKernelGGL((flux_batch_kernel<0, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
+  hipLaunchKernelGGL((recon_batch_kernel<1, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
+  hipLaunchKernelGGL((flux_batch_kernel<1, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
+  hipLaunchKernelGGL((recon_batch_kernel<2, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
+  hipLaunchKernelGGL((flux_batch_kernel<2, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
+}
+template <class R>
+static void enqueue_batch_fluxes_r(hgks_ctx b, int src_qs) {
+  if (b->tx == 64) enqueue_batch_fluxes_tx<R, 64>(b, src_qs);
+  else if (b->tx == 32) enqueue_batch_fluxes_tx<R, 32>(b, src_qs);
+  else enqueue_batch_fluxes_tx<R, 16>(b, src_qs);
+}
+static void enqueue_batch_fluxes(hgks_ctx b, int src_qs) {
+  if (precision_mixed(b->cfg)) enqueue_batch_fluxes_r<float>(b, src_qs);
+  else enqueue_batch_fluxes_r<double>(b, src_qs);
+}
+// One full batched S2O4 step on the stream (also what the graph captures).
+static void enqueue_batch_step(hgks_ctx b) {
+  const BatchTable T = b->table;
+  hipLaunchKernelGGL(begin_step_batch_kernel, dim3((T.n + 63) / 64), dim3(64), 0, b->stream, T);
+  enqueue_batch_fluxes(b, 0);
+  hipLaunchKernelGGL(update_batch_kernel<1>, dim3(b->g_update), dim3(CELL_THREADS), 0, b->stream, T);
+  enqueue_batch_fluxes(b, 1);
+  hipLaunchKernelGGL(update_batch_kernel<2>, dim3(b->g_update), dim3(CELL_THREADS), 0, b->stream, T);
+}
+
+// Milliseconds of `reps` runs of fn on the stream, timed with events.
+template <class Fn>
+static hgks_status time_on_stream(hgks_ctx b, Fn fn, int reps, float* ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(b, hipEventCreate(&e0));
+  HIP_TRY(b, hipEventCreate(&e1));
+  fn();  // warm
+  HIP_TRY(b, hipEventRecord(e0, b->stream));
+  for (int r = 0; r < reps; ++r) fn();
+  HIP_TRY(b, hipEventRecord(e1, b->stream));
+  HIP_TRY(b, hipEventSynchronize(e1));
+  HIP_TRY(b, hipGetLastError());
+  HIP_TRY(b, hipEventElapsedTime(ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return HGKS_OK;
+}
+
+static std::string tune_key(hgks_ctx b) {
+  std::string k = "hgks-batch-v1 prec=" + std::to_string(b->cfg.precision) + " n=" + std::to_string(b->members.size());
+  for (hgks_ctx m : b->members)
+    k += " " + std::to_string(m->cfg.n[0]) + "x" + std::to_string(m->cfg.n[1]) + "x" + std::to_string(m->cfg.n[2]);
+  return k;
+}
+
+// Launch-shape autotuner: persistent grid sizes for the reconstruction, flux
+// and update kernels and the flux tile width (16, 32 or 64 faces along x),
+// timed on the ensemble's own state (these kernels write only workspace).
+// Results are kept in the file named by HGKS_TUNE_CACHE when set.
+static hgks_status batch_autotune(hgks_ctx b) {
+  const char* path = std::getenv("HGKS_TUNE_CACHE");
+  const std::string key = tune_key(b);
+  if (path) {
+    if (FILE* f = std::fopen(path, "r")) {
+      char line[65536];
+      while (std::fgets(line, sizeof(line), f)) {
+        std::string l(line);
+        const size_t tab = l.find('\t');
+        if (tab == std::string::npos || l.substr(0, tab) != key) continue;
+        int tx, gr, gf, gu;
+        if (std::sscanf(l.c_str() + tab + 1, "%d %d %d %d", &tx, &gr, &gf, &gu) == 4 && gr > 0 && gf > 0 && gu > 0 &&
+            (tx == 16 || tx == 32 || tx == 64)) {
+          b->tx = tx; b->g_recon = gr; b->g_flux = gf; b->g_update = gu; b->tune_source = 2;
+          std::fclose(f);
+          return HGKS_OK;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  auto cands = [](int total) {
+    std::vector<int> c;
+    for (int g : {1024, 2048, 4096, 8192, 16384})
+      if (g < total) c.push_back(g);
+    c.push_back(total);  // one block per work item
+    return c;
+  };
+  const int max_recon = std::max(b->total_recon[0], std::max(b->total_recon[1], b->total_recon[2]));
+  float best = 1e30f, ms = 0.0f;
+  // reconstruction grid (flux shape fixed meanwhile)
+  b->tx = 16;
+  b->g_flux = b->total_flux[0][0];
+  int best_gr = max_recon;
+  for (int g : cands(max_recon)) {
+    b->g_recon = g;
+    auto fn = [&]() {
+      const BatchTable T = b->table;
+      if (precision_mixed(b->cfg)) {
+        hipLaunchKernelGGL((recon_batch_kernel<0, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+        hipLaunchKernelGGL((recon_batch_kernel<1, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+        hipLaunchKernelGGL((recon_batch_kernel<2, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+      } else {
+        hipLaunchKernelGGL((recon_batch_kernel<0, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+        hipLaunchKernelGGL((recon_batch_kernel<1, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+        hipLaunchKernelGGL((recon_batch_kernel<2, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
+      }
+    };
+    hgks_status st = time_on_stream(b, fn, 2, &ms);
+    if (st != HGKS_OK) return st;
+    if (ms < best) { best = ms; best_gr = g; }
+  }
+  b->g_recon = best_gr;
+  // flux tile width and grid (reconstruction + flux of the three directions)
+  best = 1e30f;
+  int best_tx = 16, best_gf = b->total_flux[0][0];
+  for (int ti = 0; ti < 3; ++ti) {
+    const int tx = 16 << ti;
+    const int max_flux = std::max(b->total_flux[ti][0], std::max(b->total_flux[ti][1], b->total_flux[ti][2]));
+    for (int g : cands(max_flux)) {
+      b->tx = tx;
+      b->g_flux = g;
+      hgks_status st = time_on_stream(b, [&]() { enqueue_batch_fluxes(b, 0); }, 2, &ms);
+      if (st != HGKS_OK) return st;
+      if (ms < best) { best = ms; best_tx = tx; best_gf = g; }
+    }
+  }
+  b->tx = best_tx;
+  b->g_flux = best_gf;
+  // update grid (stage 1 writes only workspace)
+  best = 1e30f;
+  int best_gu = b->total_cells;
+  for (int g : cands(b->total_cells)) {
+    auto fn = [&]() {
+      hipLaunchKernelGGL(update_batch_kernel<1>, dim3(g), dim3(CELL_THREADS), 0, b->stream, b->table);
+    };
+    hgks_status st = time_on_stream(b, fn, 3, &ms);
+    if (st != HGKS_OK) return st;
+    if (ms < best) { best = ms; best_gu = g; }
+  }
+  b->g_update = best_gu;
+  b->tune_source = 1;
+  if (path) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s\t%d %d %d %d\n", key.c_str(), b->tx, b->g_recon, b->g_flux, b->g_update);
+      std::fclose(f);
+    }
+  }
+  return HGKS_OK;
+}
 
 extern "C" {
 
@@ -991,7 +1302,7 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
 }
 
 hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
-  if (!ctx || nsteps < 0 || !std::isfinite(dt_fixed)) return HGKS_E_INVALID;
+  if (!ctx || nsteps < 0 || !std::isfinite(dt_fixed) || !ctx->members.empty()) return HGKS_E_INVALID;
   if (ctx->latched != HGKS_OK) return ctx->latched;
   const Params& P = ctx->P;
   for (int s = 0; s < nsteps; ++s) {
@@ -1016,7 +1327,7 @@ hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
 }
 
 hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out) {
-  if (!ctx || !out) return HGKS_E_INVALID;
+  if (!ctx || !out || !ctx->members.empty()) return HGKS_E_INVALID;
   const Params& P = ctx->P;
   const int nb = ctx->L.stat_blocks;
   double* fin = ctx->part + (size_t)nb * ST_COUNT;
@@ -1052,7 +1363,7 @@ hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out) {
 }
 
 hgks_status hgks_dt(hgks_ctx ctx, double* dt_out) {
-  if (!ctx || !dt_out) return HGKS_E_INVALID;
+  if (!ctx || !dt_out || !ctx->members.empty()) return HGKS_E_INVALID;
   Scalars sc;
   HIP_TRY(ctx, hipMemcpyAsync(&sc, ctx->sc, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1062,7 +1373,7 @@ hgks_status hgks_dt(hgks_ctx ctx, double* dt_out) {
 }
 
 hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* L_dev, double* dL_dev) {
-  if (!ctx || !q_dev || !L_dev || !dL_dev || !(dt > 0.0)) return HGKS_E_INVALID;
+  if (!ctx || !q_dev || !L_dev || !dL_dev || !(dt > 0.0) || !ctx->members.empty()) return HGKS_E_INVALID;
   const Params& P = ctx->P;
   hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, &ctx->sc->dt_residual, dt);
   hgks_status r = launch_fluxes_any(ctx, q_dev, 1);
@@ -1098,6 +1409,9 @@ hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int
 hgks_status hgks_destroy(hgks_ctx ctx) {
   if (!ctx) return HGKS_E_INVALID;
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (hgks_ctx m : ctx->members) hgks_destroy(m);
   delete ctx;
   return HGKS_OK;
 }
@@ -1109,5 +1423,126 @@ const char* hgks_status_string(hgks_status s) {
 }
 
 const char* hgks_last_error(hgks_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes) {
+  if (n <= 0 || !cfgs || !bytes) return HGKS_E_INVALID;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (validate(&cfgs[i], nullptr) != HGKS_OK) return HGKS_E_INVALID;
+    if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
+    total += align256(make_layout(cfgs[i]).total);
+  }
+  *bytes = total + batch_table_bytes(n);
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev, size_t ws_bytes,
+                            void* hip_stream, hgks_ctx* out) {
+  if (!out) return HGKS_E_INVALID;
+  *out = nullptr;
+  size_t need = 0;
+  if (hgks_batch_workspace_size(n, cfgs, &need) != HGKS_OK) return HGKS_E_INVALID;
+  if (!q_devs || !ws_dev || ws_bytes < need || ((uintptr_t)ws_dev & 255u) != 0) return HGKS_E_INVALID;
+  if (!hip_stream) return HGKS_E_INVALID;  // graph capture needs a created (non-default) stream
+  for (int i = 0; i < n; ++i)
+    if (!q_devs[i]) return HGKS_E_INVALID;
+  hgks_ctx b = new (std::nothrow) hgks_ctx_s();
+  if (!b) return HGKS_E_NOMEM;
+  b->cfg = cfgs[0];
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ws = static_cast<char*>(ws_dev);
+  b->ws_bytes = ws_bytes;
+  b->latched = HGKS_OK;
+  char* base = static_cast<char*>(ws_dev);
+  size_t off = 0;
+  std::vector<BatchEntry> host(n);
+  std::vector<int> pre((size_t)PRE_ROWS * (n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    const size_t sz = align256(make_layout(cfgs[i]).total);
+    hgks_ctx m = nullptr;
+    hgks_status st = hgks_init(&cfgs[i], q_devs[i], base + off, sz, hip_stream, 0.0, &m);
+    if (st != HGKS_OK) {
+      b->err = "member " + std::to_string(i) + ": " + (m ? m->err : std::string("init failed"));
+      hgks_destroy(b);
+      return st;
+    }
+    b->members.push_back(m);
+    off += sz;
+    BatchEntry& e = host[i];
+    e.P = m->P;
+    e.q = m->q;
+    e.qs = m->qs;
+    e.acc = m->acc;
+    e.B = m->B;
+    for (int d = 0; d < 3; ++d) e.F[d] = m->F[d];
+    e.sc = m->sc;
+    e.qref = m->qref;
+    e.cfl = cfgs[i].cfl;
+    const int rec[3] = {recon_tiles<0>(m->P), recon_tiles<1>(m->P), recon_tiles<2>(m->P)};
+    for (int d = 0; d < 3; ++d) {
+      pre[(size_t)(PRE_RECON + d) * (n + 1) + i + 1] = pre[(size_t)(PRE_RECON + d) * (n + 1) + i] + rec[d];
+      const int fl[3] = {flux_tiles<16>(m->P, d), flux_tiles<32>(m->P, d), flux_tiles<64>(m->P, d)};
+      for (int t = 0; t < 3; ++t) {
+        const size_t row = (size_t)(PRE_FLUX + 3 * t + d) * (n + 1);
+        pre[row + i + 1] = pre[row + i] + fl[t];
+      }
+    }
+    pre[(size_t)PRE_CELL * (n + 1) + i + 1] = pre[(size_t)PRE_CELL * (n + 1) + i] + (int)cell_blocks(m->P);
+  }
+  for (int d = 0; d < 3; ++d) {
+    b->total_recon[d] = pre[(size_t)(PRE_RECON + d) * (n + 1) + n];
+    for (int t = 0; t < 3; ++t) b->total_flux[t][d] = pre[(size_t)(PRE_FLUX + 3 * t + d) * (n + 1) + n];
+  }
+  b->total_cells = pre[(size_t)PRE_CELL * (n + 1) + n];
+  BatchEntry* dE = reinterpret_cast<BatchEntry*>(base + off);
+  int* dpre = reinterpret_cast<int*>(base + off + align256((size_t)n * sizeof(BatchEntry)));
+  HIP_TRY(b, hipMemcpyAsync(dE, host.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipStreamSynchronize(b->stream));
+  b->table.E = dE;
+  b->table.pre = dpre;
+  b->table.n = n;
+  hgks_status st = batch_autotune(b);
+  if (st != HGKS_OK) {
+    hgks_destroy(b);
+    return st;
+  }
+  // capture one step
+  HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+  enqueue_batch_step(b);
+  HIP_TRY(b, hipStreamEndCapture(b->stream, &b->graph));
+  HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  *out = b;
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_step(hgks_ctx ctx, int32_t nsteps) {
+  if (!ctx || nsteps < 0 || ctx->members.empty() || !ctx->exec) return HGKS_E_INVALID;
+  for (hgks_ctx m : ctx->members)
+    if (m->latched != HGKS_OK) return m->latched;
+  for (int s = 0; s < nsteps; ++s) HIP_TRY(ctx, hipGraphLaunch(ctx->exec, ctx->stream));
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_stats(hgks_ctx ctx, int32_t i, hgks_stats_t* out) {
+  if (!ctx || !out || i < 0 || i >= (int32_t)ctx->members.size()) return HGKS_E_INVALID;
+  hgks_ctx m = ctx->members[i];
+  const hgks_status st = hgks_stats(m, out);
+  if (st != HGKS_OK) ctx->err = m->err;
+  return st;
+}
+
+hgks_status hgks_batch_info(hgks_ctx ctx, int64_t info[8]) {
+  if (!ctx || !info || ctx->members.empty()) return HGKS_E_INVALID;
+  info[0] = (int64_t)ctx->members.size();
+  info[1] = ctx->tx;
+  info[2] = ctx->g_recon;
+  info[3] = ctx->g_flux;
+  info[4] = ctx->g_update;
+  info[5] = ctx->tune_source;
+  info[6] = (int64_t)ctx->total_recon[0] + ctx->total_recon[1] + ctx->total_recon[2];
+  info[7] = ctx->total_cells;
+  return HGKS_OK;
+}
 
 }  // extern "C"

@@ -23,6 +23,7 @@ FP64, MIXED = 0, 1
 EXPORTED = [
     "hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
     "hgks_destroy", "hgks_status_string", "hgks_last_error", "hgks_profile", "hgks_profile_read",
+    "hgks_batch_workspace_size", "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info",
 ]
 PROFILE_CLASSES = ("recon", "flux", "update", "other")
 
@@ -92,6 +93,11 @@ def lib():
         L.hgks_dt.argtypes = [vp, ctypes.POINTER(d)]
         L.hgks_residual.argtypes = [vp, vp, d, vp, vp]
         L.hgks_destroy.argtypes = [vp]
+        L.hgks_batch_workspace_size.argtypes = [i32, C, ctypes.POINTER(sz)]
+        L.hgks_batch_init.argtypes = [i32, C, ctypes.POINTER(vp), vp, sz, vp, ctypes.POINTER(vp)]
+        L.hgks_batch_step.argtypes = [vp, i32]
+        L.hgks_batch_stats.argtypes = [vp, i32, ctypes.POINTER(hgks_stats_t)]
+        L.hgks_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.hgks_profile.argtypes = [vp, i32]
         L.hgks_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.hgks_status_string.argtypes = [i32]
@@ -99,7 +105,8 @@ def lib():
         L.hgks_last_error.argtypes = [vp]
         L.hgks_last_error.restype = ctypes.c_char_p
         for f in ("hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
-                  "hgks_destroy", "hgks_profile", "hgks_profile_read"):
+                  "hgks_destroy", "hgks_profile", "hgks_profile_read", "hgks_batch_workspace_size",
+                  "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -189,6 +196,51 @@ def hgks_profile_read(ctx) -> dict:
     return {PROFILE_CLASSES[c]: (float(ms[c]), int(n[c])) for c in range(4)}
 
 
+def _cfg_array(cfgs):
+    arr = (hgks_config * len(cfgs))()
+    for i, c in enumerate(cfgs):
+        arr[i] = c
+    return arr
+
+
+def hgks_batch_workspace_size(cfgs) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hgks_batch_workspace_size(len(cfgs), _cfg_array(cfgs), ctypes.byref(n)))
+    return int(n.value)
+
+
+def hgks_batch_init(cfgs, q_ptrs, ws_ptr: int, ws_bytes: int, stream_ptr: int):
+    ctx = ctypes.c_void_p(0)
+    qs = (ctypes.c_void_p * len(q_ptrs))(*[ctypes.c_void_p(p) for p in q_ptrs])
+    _check(lib().hgks_batch_init(len(cfgs), _cfg_array(cfgs), qs, ctypes.c_void_p(ws_ptr), ws_bytes,
+                                 ctypes.c_void_p(stream_ptr), ctypes.byref(ctx)))
+    return ctx
+
+
+def hgks_batch_step(ctx, nsteps: int):
+    _check(lib().hgks_batch_step(ctx, int(nsteps)), ctx)
+
+
+def hgks_batch_stats(ctx, i: int) -> dict:
+    s = hgks_stats_t()
+    _check(lib().hgks_batch_stats(ctx, int(i), ctypes.byref(s)), ctx)
+    return {
+        "t": s.t, "dt_last": s.dt_last, "steps": s.steps, "Ek": s.Ek, "eps_sol": s.eps_sol,
+        "eps_dil": s.eps_dil, "eps_com": s.eps_com, "total": np.array(s.total[:]),
+        "max_abs": np.array(s.max_abs[:]), "min_p": s.min_p, "min_rho": s.min_rho, "nonfinite": s.nonfinite,
+    }
+
+
+BATCH_INFO_KEYS = ("instances", "flux_tile_x", "grid_recon", "grid_flux", "grid_update", "tune_source",
+                   "recon_tiles", "cell_blocks")
+
+
+def hgks_batch_info(ctx) -> dict:
+    info = (ctypes.c_int64 * 8)()
+    _check(lib().hgks_batch_info(ctx, info), ctx)
+    return dict(zip(BATCH_INFO_KEYS, [int(x) for x in info]))
+
+
 def hgks_destroy(ctx):
     _check(lib().hgks_destroy(ctx))
 
@@ -238,6 +290,60 @@ class Solver:
     def state(self) -> np.ndarray:
         self.stream.synchronize()
         return self.q.cpu().numpy()
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            hgks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """An ensemble of independent instances advanced together (one launch per
+    kernel over all instances' tiles, each step a replayed HIP graph, each
+    instance with its own CFL time step).  States are torch float64 tensors;
+    the workspace and a dedicated stream come from torch."""
+
+    def __init__(self, params_list, q0_list, precision: int = FP64, device: str = "cuda:0"):
+        import torch
+
+        self.params = list(params_list)
+        self.cfgs = [make_config(p, precision) for p in self.params]
+        self.q = []
+        for p, q0 in zip(self.params, q0_list):
+            nx, ny, nz = p["n"]
+            t = torch.as_tensor(np.ascontiguousarray(q0) if isinstance(q0, np.ndarray) else q0,
+                                dtype=torch.float64, device=device).contiguous().clone()
+            assert tuple(t.shape) == (5, nz, ny, nx), t.shape
+            self.q.append(t)
+        self.ws_bytes = hgks_batch_workspace_size(self.cfgs)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+        self.stream = torch.cuda.Stream(device=device)
+        torch.cuda.synchronize(device)
+        self.ctx = hgks_batch_init(self.cfgs, [t.data_ptr() for t in self.q], self.ws_ptr, self.ws_bytes,
+                                   self.stream.cuda_stream)
+
+    def step(self, nsteps: int = 1):
+        hgks_batch_step(self.ctx, nsteps)
+
+    def stats(self, i: int) -> dict:
+        return hgks_batch_stats(self.ctx, i)
+
+    def info(self) -> dict:
+        return hgks_batch_info(self.ctx)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def state(self, i: int) -> np.ndarray:
+        self.stream.synchronize()
+        return self.q[i].cpu().numpy()
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

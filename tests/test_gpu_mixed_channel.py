@@ -48,12 +48,17 @@ def test_mixed_precision_error_is_small_and_stated(hg, oracle, ma):
     st = s.stats()
     s.close()
     err = rel_err(got, ref)
+    # momentum components against the momentum magnitude (rho W starts at zero,
+    # so its own max-norm is not a meaningful scale)
+    mscale = np.sqrt((ref[1:4] ** 2).sum(axis=0)).max()
+    merr = np.abs(got[1:4] - ref[1:4]).max(axis=(1, 2, 3)) / mscale
     so = oracle.stats(p, ref)
     eEk = abs(st["Ek"] - so["Ek"]) / so["Ek"]
     eeps = abs(st["eps_com"] - so["eps_com"]) / so["eps_com"]
-    say(f"mixed TGV32 Ma={ma}: state rel err {err}, E_k rel err {eEk:.2e}, eps_com rel err {eeps:.2e}")
+    say(f"mixed TGV32 Ma={ma}: state rel err per component {err}, momentum vs |m|max {merr}, "
+        f"E_k rel err {eEk:.2e}, eps_com rel err {eeps:.2e}")
     assert np.isfinite(got).all()
-    assert (err <= 1e-4).all(), err
+    assert err[0] <= 1e-5 and err[4] <= 1e-5 and (merr <= 1e-5).all(), (err, merr)
     assert eEk <= 1e-5 and eeps <= 1e-3
 
 
