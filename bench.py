@@ -42,7 +42,13 @@ FLOPS_RECON_PER_FACE = 6630.0
 # same counter reads for a device copy of known size (bench.py
 # --copy-calibration).  Valid only for the kernel sources it was measured on:
 # `traffic` is reported as null when their hash differs.
-TRAFFIC_MEASURED = None  # {"sources_sha256": ..., "fetch_bytes": ..., "write_bytes": ...}
+# Mean of the three FP64 directions:
+TRAFFIC_MEASURED = {
+    "n": 256,
+    "sources_sha256": "abdd776e3a8893f200d16cef01f073fc28975dbf580448dc6987feaeb24c5f51",
+    "fetch_bytes": 1.2606e+10,
+    "write_bytes": 1.4365e+09,
+}
 
 # MI355X published peaks
 PEAK_FP64_VECTOR_TFLOPS = 78.6
@@ -166,8 +172,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run beside FP64")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--ensemble", action="store_true",
                     help="measure the 64-instance ensemble (batched vs per-instance loop) instead")
@@ -194,54 +201,54 @@ def main() -> int:
         return 0
     n = args.n
     p = tgv_workload(n)
-    prec = hgks.FP64 if args.precision == "fp64" else hgks.MIXED
     print(f"# building TGV {n}^3 initial state", file=sys.stderr, flush=True)
     q0 = W.tgv_initial(p)
-    solver = hgks.Solver(p, q0, precision=prec)
-    del q0
 
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    solver.step(args.warmup, 0.0)
-    torch.cuda.synchronize()
+    def run(prec_name: str):
+        """Warmup, then K timed CFL steps with per-kernel event timing."""
+        prec = hgks.FP64 if prec_name == "fp64" else hgks.MIXED
+        solver = hgks.Solver(p, q0, precision=prec)
+        print(f"# {prec_name}: warmup {args.warmup} steps", file=sys.stderr, flush=True)
+        solver.step(args.warmup, 0.0)
+        torch.cuda.synchronize()
+        hgks.hgks_profile(solver.ctx, True)
+        hgks.hgks_profile_read(solver.ctx)  # clear
+        print(f"# {prec_name}: timing {args.steps} steps", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.step(args.steps, 0.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = hgks.hgks_profile_read(solver.ctx)
+        hgks.hgks_profile(solver.ctx, False)
+        st = solver.stats()
+        if st["nonfinite"] or not (st["min_p"] > 0):
+            raise RuntimeError(f"{prec_name}: state became invalid during the benchmark")
+        flux_ms, flux_n = prof["flux"]
+        faces_per_launch = (n + 1) * n * n
+        achieved = FLOPS_FLUX_PER_FACE * faces_per_launch / (flux_ms / flux_n / 1e3) / 1e12
+        peak = PEAK_FP64_VECTOR_TFLOPS if prec == hgks.FP64 else PEAK_FP32_VECTOR_TFLOPS
+        roofline = {
+            "bound": "alu",
+            "kernel": "flux_kernel (2nd tangential WENO-Z sweep + Gauss-point BGK flux + face assembly)",
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(n) if prec == hgks.FP64 else None,
+            "avg_launch_ms": round(flux_ms / flux_n, 4),
+            "flops_per_face": FLOPS_FLUX_PER_FACE,
+            "faces_per_launch": faces_per_launch,
+            "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+        }
+        elapsed = t1 - t0
+        state = solver.state()
+        solver.close()
+        return elapsed, roofline, st, state
 
-    hgks.hgks_profile(solver.ctx, True)
-    hgks.hgks_profile_read(solver.ctx)  # clear
-    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(args.steps, 0.0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = hgks.hgks_profile_read(solver.ctx)
-    hgks.hgks_profile(solver.ctx, False)
-    st = solver.stats()
-    if st["nonfinite"] or not (st["min_p"] > 0):
-        print("# state became invalid during the benchmark", file=sys.stderr)
-        return 1
-
-    elapsed = t1 - t0
+    elapsed, roofline, st, state64 = run("fp64")
     cell_stages = 2.0 * n ** 3 * args.steps
     value = cell_stages / elapsed
-
-    flux_ms, flux_n = prof["flux"]
-    faces_per_launch = (n + 1) * n * n
-    flux_avg_s = flux_ms / flux_n / 1e3
-    achieved = FLOPS_FLUX_PER_FACE * faces_per_launch / flux_avg_s / 1e12
-    peak = PEAK_FP64_VECTOR_TFLOPS if prec == hgks.FP64 else PEAK_FP32_VECTOR_TFLOPS
-    roofline = {
-        "bound": "alu",
-        "kernel": "flux_kernel (2nd tangential WENO-Z sweep + Gauss-point BGK flux + face assembly)",
-        "achieved": round(achieved, 3),
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4),
-        "traffic": measured_traffic(n),
-        "avg_launch_ms": round(flux_ms / flux_n, 4),
-        "flops_per_face": FLOPS_FLUX_PER_FACE,
-        "faces_per_launch": faces_per_launch,
-        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
-    }
-
     out = {
         "metric": METRIC,
         "value": value,
@@ -253,22 +260,40 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == hgks.FP64 else "f32-recon-flux/f64-state",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"Taylor-Green vortex {n}^3 periodic on [0,2pi]^3, Ma 0.29, Re 1600, Pr 0.72, "
                         f"CFL 0.5 (CFL time step each step)",
             "n": n,
-            "precision": args.precision,
+            "precision": "fp64",
             "parallelism": "single GPU",
             "simulated_time": st["t"],
         },
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        m_elapsed, m_roof, m_st, state_m = run("mixed")
+        # stated error of the mixed path against the FP64 path at matched steps
+        rel = (abs(state_m - state64).max(axis=(1, 2, 3)) / abs(state64).max(axis=(1, 2, 3)))
+        mom = abs(state_m[1:4] - state64[1:4]).max() / ((state64[1:4] ** 2).sum(axis=0) ** 0.5).max()
+        out["mixed"] = {
+            "value": cell_stages / m_elapsed,
+            "ms_per_step": m_elapsed / args.steps * 1e3,
+            "speedup_vs_fp64": elapsed / m_elapsed,
+            "dtype": "f32 reconstruction and flux on deviations from the mean state, f64 state/update/reductions",
+            "error_vs_fp64": {
+                "after_steps": args.warmup + args.steps,
+                "state_rel_maxnorm": [float(x) for x in rel],
+                "momentum_rel_to_max_speed": float(mom),
+                "Ek_rel": abs(m_st["Ek"] - st["Ek"]) / st["Ek"],
+                "eps_com_rel": abs(m_st["eps_com"] - st["eps_com"]) / st["eps_com"],
+            },
+            "roofline": m_roof,
+        }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
-    solver.close()
     print(json.dumps(out), flush=True)
     return 0
 
