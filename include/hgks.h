@@ -135,13 +135,18 @@ hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int
 
 /* ---- Batched ensemble ----------------------------------------------------
  * Many independent instances (each its own grid size, gas and state) advanced
- * together: every kernel of a step is one launch over the tiles of all
- * instances (a persistent grid striding a tile table), each S2O4 step is
- * captured once in a HIP graph and replayed, and each instance takes its own
- * CFL time step.  Instance i's state q_devs[i] has the single-instance layout.
- * For the callers running many small problems in one stream (ensembles,
- * parameter sweeps).  Errors: HGKS_E_INVALID for any invalid member config
- * (its index is reported by hgks_last_error), HGKS_E_DEVICE. */
+ * together: every phase of a step is one launch over the concatenated tile
+ * work list of all instances (or of a group of consecutive instances whose
+ * reconstruction buffers fit a cache budget; the autotuner picks the budget and
+ * the flux tile width at init, timing the candidates on the ensemble's own
+ * state), each S2O4 step is captured once in a HIP graph and replayed, and
+ * each instance takes its own CFL time step.  Instance i's state q_devs[i] has
+ * the single-instance layout, and each instance's arithmetic is that of a
+ * single-instance run.  For the callers running many small problems in one
+ * stream (ensembles, parameter sweeps).  ws_dev must be 256-byte aligned and
+ * hip_stream a created stream (graph capture).  Errors: HGKS_E_INVALID for any
+ * invalid member config (its index is reported by hgks_last_error), or work
+ * lists beyond 2^30 tiles; HGKS_E_DEVICE. */
 hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes);
 hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev,
                             size_t ws_bytes, void* hip_stream, hgks_ctx* out);
@@ -151,9 +156,11 @@ hgks_status hgks_batch_step(hgks_ctx ctx, int32_t nsteps);
 /* Statistics of instance i (synchronises the stream). */
 hgks_status hgks_batch_stats(hgks_ctx ctx, int32_t i, hgks_stats_t* out);
 /* Launch shapes chosen by the autotuner: info = {instances, flux tile width
- * (faces along x), reconstruction grid, flux grid, update grid, source (1
- * tuned now, 2 read from the file named by HGKS_TUNE_CACHE), reconstruction
- * tiles per step (3 directions), cell blocks}. */
+ * (faces along x), member-group budget for the reconstruction buffers in MiB
+ * (0: all instances in one group), number of groups, flux tiles per stage (3
+ * directions), source (1 tuned now, 2 read from the file named by
+ * HGKS_TUNE_CACHE), reconstruction tiles per stage (3 directions), cell
+ * blocks}. */
 hgks_status hgks_batch_info(hgks_ctx ctx, int64_t info[8]);
 
 /* Release the host context (device memory stays the caller's). */

@@ -53,6 +53,15 @@ struct Scalars {
   unsigned long long pad[3];
 };
 
+// Global-memory view of a device pointer.  A pointer that a kernel reads out
+// of memory (the batched kernels take theirs from the instance table) is a
+// generic pointer to the compiler, which then emits flat accesses; flat loads
+// share the wait counter of LDS traffic, so every LDS wait would also wait for
+// outstanding HBM loads.  Accessing through an address-space-1 pointer gives
+// global loads and stores.
+#define HGKS_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ HGKS_GLOBAL T* gmem(T* p) { return (HGKS_GLOBAL T*)p; }
+
 __host__ __device__ inline size_t cells(const Params& P) { return (size_t)P.n[0] * P.n[1] * P.n[2]; }
 
 // Face extents of direction d: one more face than cells along d (on a
@@ -114,7 +123,7 @@ __device__ __forceinline__ void load_cell(const double* __restrict__ q, const Pa
   const size_t n3 = cells(P);
   const size_t idx = ((size_t)c[2] * P.n[1] + c[1]) * P.n[0] + c[0];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) v[k] = q[k * n3 + idx];
+  for (int k = 0; k < 5; ++k) v[k] = gmem(q)[k * n3 + idx];
   if (mirror) {
     double rho = v[0], ir = 1.0 / rho;
     double U = v[1] * ir, V = v[2] * ir, W = v[3] * ir;
@@ -181,7 +190,7 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   // reference state subtracted before the reconstruction (zero on the FP64 path)
   double ref[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) ref[k] = qref[k];
+  for (int k = 0; k < 5; ++k) ref[k] = gmem(qref)[k];
   double rl[5];
   rl[0] = ref[0];
   rl[1] = ref[1 + DIR];
@@ -246,7 +255,7 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   }
   const size_t NB = (size_t)be[0] * be[1] * be[2];
   const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * be[0] + (f[0] - bo[0]);
-  R* out = B + (size_t)g1 * NB + bidx;
+  HGKS_GLOBAL R* out = gmem(B) + (size_t)g1 * NB + bidx;
   const size_t qstride = 2 * NB;
   GaussPoint<R> gp(g1);
 #pragma unroll
@@ -340,15 +349,17 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     bi[j] = (size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0]);
   }
   GaussPoint<R> gp(g2);
-  const R sn = R(P.dface[DIR][f[DIR]]);
-  const R st1 = R(P.dgp[D1][2 * f[D1] + g1]);
-  const R st2 = R(P.dgp[D2][2 * f[D2] + g2]);
+  const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
+  const R st1 = R(gmem(P.dgp[D1])[2 * f[D1] + g1]);
+  const R st2 = R(gmem(P.dgp[D2])[2 * f[D2] + g2]);
+  const HGKS_GLOBAL R* Bg = gmem(B);
+  const HGKS_GLOBAL double* qrg = gmem(qref);
   double rl[5];
-  rl[0] = qref[0];
-  rl[1] = qref[1 + DIR];
-  rl[2] = qref[1 + D1];
-  rl[3] = qref[1 + D2];
-  rl[4] = qref[4];
+  rl[0] = qrg[0];
+  rl[1] = qrg[1 + DIR];
+  rl[2] = qrg[1 + D1];
+  rl[3] = qrg[1 + D2];
+  rl[4] = qrg[4];
   GasParams<R> g;
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
@@ -359,7 +370,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   // Five stencil values of quantity qi along t2.
   auto stencil = [&](int qi, R v[5]) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = B[qi * qstride + bi[j]];
+    for (int j = 0; j < 5; ++j) v[j] = Bg[qi * qstride + bi[j]];
   };
 
   // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
@@ -437,7 +448,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     s2[k] += __shfl_xor(s2[k], 32);
   }
   if (!valid || gpi != 0) return;  // this lane only
-  const double area = P.hcell[D1][f[D1]] * P.hcell[D2][f[D2]];
+  const double area = gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -450,10 +461,11 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fe[0] + f[0];
   // rotate momentum back to the global frame
   const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
+  HGKS_GLOBAL double* Fg = gmem(F);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    F[gcomp[k] * NF + fi] = loc[k];
-    F[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
+    Fg[gcomp[k] * NF + fi] = loc[k];
+    Fg[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
   }
 }
 
@@ -473,8 +485,8 @@ __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, con
                                               const Params& P, int i, int j, int k, double L[5], double dL[5]) {
   const size_t n3 = cells(P);
   const size_t c = ((size_t)k * P.n[1] + j) * P.n[0] + i;
-  const double vol = P.hcell[0][i] * P.hcell[1][j] * P.hcell[2][k];
-  const double* Fd[3] = {F0, F1, F2};
+  const double vol = gmem(P.hcell[0])[i] * gmem(P.hcell[1])[j] * gmem(P.hcell[2])[k];
+  const HGKS_GLOBAL double* Fd[3] = {gmem(F0), gmem(F1), gmem(F2)};
 #pragma unroll
   for (int m = 0; m < 5; ++m) { L[m] = 0.0; dL[m] = 0.0; }
 #pragma unroll
@@ -491,7 +503,8 @@ __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, con
       dL[m] -= (Fd[d][(5 + m) * NF + fp] - Fd[d][(5 + m) * NF + fm]) / vol;
     }
   }
-  const double rho = qe[c], mx = qe[n3 + c], my = qe[2 * n3 + c], mz = qe[3 * n3 + c];
+  const HGKS_GLOBAL double* qg = gmem(qe);
+  const double rho = qg[c], mx = qg[n3 + c], my = qg[2 * n3 + c], mz = qg[3 * n3 + c];
   const double lrho = L[0];
   L[1] += rho * P.force[0];
   L[2] += rho * P.force[1];
@@ -509,9 +522,9 @@ __device__ __forceinline__ double cell_wave_rate(const double v[5], const Params
   double U = v[1] * ir, V = v[2] * ir, W = v[3] * ir;
   double p = P.gm1 * (v[4] - 0.5 * v[0] * (U * U + V * V + W * W));
   double c = sqrt(P.gamma * p * ir);
-  double r = (fabs(U) + c) / P.hcell[0][i];
-  r = fmax(r, (fabs(V) + c) / P.hcell[1][j]);
-  r = fmax(r, (fabs(W) + c) / P.hcell[2][k]);
+  double r = (fabs(U) + c) / gmem(P.hcell[0])[i];
+  r = fmax(r, (fabs(V) + c) / gmem(P.hcell[1])[j]);
+  r = fmax(r, (fabs(W) + c) / gmem(P.hcell[2])[k]);
   return r;
 }
 
@@ -541,28 +554,31 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
                                              size_t blk) {
   const size_t n3 = cells(P);
   const size_t c = blk * CELL_THREADS + threadIdx.x;
+  HGKS_GLOBAL double* qg = gmem(q);
+  HGKS_GLOBAL double* qsg = gmem(qs);
+  HGKS_GLOBAL double* accg = gmem(acc);
   double rate = 0.0;
   if (c < n3) {
     const int i = (int)(c % P.n[0]);
     const int j = (int)((c / P.n[0]) % P.n[1]);
     const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
-    const double dt = sc->dt;
+    const double dt = gmem(sc)->dt;
     double L[5], dL[5];
     if (STAGE == 1) {
       cell_residual(q, F0, F1, F2, P, i, j, k, L, dL);
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        const double qn = q[m * n3 + c];
-        qs[m * n3 + c] = qn + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m];
-        acc[m * n3 + c] = qn + dt * L[m] + dt * dt / 6.0 * dL[m];
+        const double qn = qg[m * n3 + c];
+        qsg[m * n3 + c] = qn + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m];
+        accg[m * n3 + c] = qn + dt * L[m] + dt * dt / 6.0 * dL[m];
       }
     } else {
       cell_residual(qs, F0, F1, F2, P, i, j, k, L, dL);
       double v[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        v[m] = acc[m * n3 + c] + dt * dt / 3.0 * dL[m];
-        q[m * n3 + c] = v[m];
+        v[m] = accg[m * n3 + c] + dt * dt / 3.0 * dL[m];
+        qg[m * n3 + c] = v[m];
       }
       rate = cell_wave_rate(v, P, i, j, k);
     }
@@ -748,77 +764,58 @@ struct BatchEntry {
   double* qref;
   double cfl;
 };
-enum { PRE_RECON = 0, PRE_FLUX = 3, PRE_CELL = 12, PRE_ROWS = 13 };  // flux rows: TX 16, 32, 64 x 3 directions
-template <int TX> constexpr int flux_row(int d) { return PRE_FLUX + 3 * (TX == 16 ? 0 : (TX == 32 ? 1 : 2)) + d; }
+enum { PRE_RECON = 0, PRE_FLUX = 3, PRE_CELL = 9, PRE_ROWS = 10 };  // flux rows: TX 16, 32 x 3 directions
+template <int TX> constexpr int flux_row(int d) { return PRE_FLUX + 3 * (TX == 16 ? 0 : 1) + d; }
 
 struct BatchTable {
   const BatchEntry* E;
-  const int* pre;  // [PRE_ROWS][n + 1]
+  const int* pre;     // [PRE_ROWS][n + 1]: prefix sums of the members' work items
+  const int* coarse;  // per row: the member holding item k << BATCH_COARSE_SHIFT
+  int coarse_off[PRE_ROWS];
   int n;
 };
+constexpr int BATCH_COARSE_SHIFT = 6;
 
-__device__ __forceinline__ int find_instance(const int* pre, int n, int t) {
-  int lo = 0, hi = n;  // pre[lo] <= t < pre[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= t) lo = mid;
-    else hi = mid;
-  }
-  return lo;
+// Member holding item t of work-list row `row`, and t's index within it: the
+// coarse table gives the member of item (t >> 6) << 6, then a forward step
+// over members that end before t (every member has at least one item).
+__device__ __forceinline__ int find_instance(const BatchTable& T, int row, int t, int& local) {
+  const int* pre = T.pre + row * (T.n + 1);
+  int inst = T.coarse[T.coarse_off[row] + (t >> BATCH_COARSE_SHIFT)];
+  while (t >= pre[inst + 1]) ++inst;
+  local = t - pre[inst];
+  return inst;
 }
 
-// Contiguous chunk [t0, t1) of a work list of `total` items for this block of
-// a persistent grid; blocks are XCD-remapped so neighbouring chunks share an L2.
-__device__ __forceinline__ void block_chunk(int total, int& t0, int& t1) {
-  const int G = gridDim.x;
-  const int lb = xcd_linear_block(G);
-  const int chunk = (total + G - 1) / G;
-  t0 = min(total, lb * chunk);
-  t1 = min(total, t0 + chunk);
-}
-
+// The batched kernels run one block per work item of the slice [t0, t1) of
+// the concatenated work list (all members, or a group of consecutive members);
+// blocks are XCD-remapped so each XCD's L2 holds neighbouring tiles.
 template <int DIR, class R>
-__global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T, int src_qs) {
+__global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T, int t0, int t1, int src_qs) {
   __shared__ R A[25][recon_lds_faces<DIR>()];
-  const int* pre = T.pre + (PRE_RECON + DIR) * (T.n + 1);
-  int t0, t1;
-  block_chunk(pre[T.n], t0, t1);
-  if (t0 >= t1) return;
-  int inst = find_instance(pre, T.n, t0);
-  for (int t = t0; t < t1; ++t) {
-    while (t >= pre[inst + 1]) ++inst;
-    const BatchEntry& e = T.E[inst];
-    __syncthreads();  // the previous tile's reads of A are complete
-    recon_tile<DIR, R>(src_qs ? e.qs : e.q, e.P, e.qref, static_cast<R*>(e.B), t - pre[inst], A);
-  }
+  const int t = t0 + xcd_linear_block(gridDim.x);
+  if (t >= t1) return;
+  int local;
+  const BatchEntry& e = T.E[find_instance(T, PRE_RECON + DIR, t, local)];
+  recon_tile<DIR, R>(src_qs ? e.qs : e.q, e.P, e.qref, static_cast<R*>(e.B), local, A);
 }
 
 template <int DIR, class R, int TX>
-__global__ __launch_bounds__(FLUX_THREADS) void flux_batch_kernel(BatchTable T) {
-  const int* pre = T.pre + flux_row<TX>(DIR) * (T.n + 1);
-  int t0, t1;
-  block_chunk(pre[T.n], t0, t1);
-  if (t0 >= t1) return;
-  int inst = find_instance(pre, T.n, t0);
-  for (int t = t0; t < t1; ++t) {
-    while (t >= pre[inst + 1]) ++inst;
-    const BatchEntry& e = T.E[inst];
-    flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, e.sc->dt, e.F[DIR], t - pre[inst]);
-  }
+__global__ __launch_bounds__(FLUX_THREADS) void flux_batch_kernel(BatchTable T, int t0, int t1) {
+  const int t = t0 + xcd_linear_block(gridDim.x);
+  if (t >= t1) return;
+  int local;
+  const BatchEntry& e = T.E[find_instance(T, flux_row<TX>(DIR), t, local)];
+  flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T) {
-  const int* pre = T.pre + PRE_CELL * (T.n + 1);
-  int t0, t1;
-  block_chunk(pre[T.n], t0, t1);
-  if (t0 >= t1) return;
-  int inst = find_instance(pre, T.n, t0);
-  for (int t = t0; t < t1; ++t) {
-    while (t >= pre[inst + 1]) ++inst;
-    const BatchEntry& e = T.E[inst];
-    update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, (size_t)(t - pre[inst]));
-  }
+__global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T, int t0, int t1) {
+  const int t = t0 + xcd_linear_block(gridDim.x);
+  if (t >= t1) return;
+  int local;
+  const BatchEntry& e = T.E[find_instance(T, PRE_CELL, t, local)];
+  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, (size_t)local);
 }
 
 // Start of a batched step: each instance takes its own CFL time step.
@@ -948,8 +945,9 @@ struct hgks_ctx_s {
   // tuned launch shapes and the captured step
   std::vector<hgks_ctx> members;
   BatchTable table{};
-  int total_recon[3] = {0, 0, 0}, total_flux[3][3] = {{0}}, total_cells = 0;
-  int tx = 16, g_recon = 0, g_flux = 0, g_update = 0, tune_source = 0;
+  std::vector<int> pre;          // host copy of the prefix rows
+  std::vector<int> group_first;  // member groups [group_first[g], group_first[g + 1])
+  int tx = 16, group_mib = 0, tune_source = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1046,38 +1044,113 @@ static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CEL
 
 // ---- batched ensemble: host side ------------------------------------------
 
-static size_t batch_table_bytes(int n) {
-  return align256((size_t)n * sizeof(BatchEntry)) + align256((size_t)PRE_ROWS * (n + 1) * sizeof(int));
+// Work-list prefix rows of a batch: per member, the reconstruction tiles of
+// each direction, the flux tiles of each direction for tile widths 16 and 32,
+// and the cell blocks.  Empty when a row's total does not fit an int.
+static std::vector<int> batch_prefix(int n, const hgks_config* cfgs) {
+  std::vector<int> pre((size_t)PRE_ROWS * (n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    Params P{};
+    for (int a = 0; a < 3; ++a) { P.n[a] = cfgs[i].n[a]; P.bc[a] = cfgs[i].bc[a]; }
+    long long items[PRE_ROWS];
+    items[PRE_RECON + 0] = recon_tiles<0>(P);
+    items[PRE_RECON + 1] = recon_tiles<1>(P);
+    items[PRE_RECON + 2] = recon_tiles<2>(P);
+    for (int d = 0; d < 3; ++d) {
+      items[flux_row<16>(d)] = flux_tiles<16>(P, d);
+      items[flux_row<32>(d)] = flux_tiles<32>(P, d);
+    }
+    items[PRE_CELL] = (long long)((cells(P) + CELL_THREADS - 1) / CELL_THREADS);
+    for (int r = 0; r < PRE_ROWS; ++r) {
+      const long long v = (long long)pre[(size_t)r * (n + 1) + i] + items[r];
+      if (v > INT32_MAX / 2) return {};
+      pre[(size_t)r * (n + 1) + i + 1] = (int)v;
+    }
+  }
+  return pre;
 }
 
+// Coarse member table of every row: entry k names the member holding item
+// k << BATCH_COARSE_SHIFT; off[r] is where row r starts.
+static std::vector<int> batch_coarse(int n, const std::vector<int>& pre, int off[PRE_ROWS]) {
+  std::vector<int> c;
+  for (int r = 0; r < PRE_ROWS; ++r) {
+    off[r] = (int)c.size();
+    const int* p = pre.data() + (size_t)r * (n + 1);
+    int inst = 0;
+    for (int t = 0; t < p[n]; t += 1 << BATCH_COARSE_SHIFT) {
+      while (t >= p[inst + 1]) ++inst;
+      c.push_back(inst);
+    }
+  }
+  return c;
+}
+
+static size_t batch_table_bytes(int n, size_t coarse_entries) {
+  return align256((size_t)n * sizeof(BatchEntry)) + align256((size_t)PRE_ROWS * (n + 1) * sizeof(int)) +
+         align256(coarse_entries * sizeof(int));
+}
+
+// First item of member m in row r (m = n: the row's total).
+static int batch_item(hgks_ctx b, int r, int m) { return b->pre[(size_t)r * (b->members.size() + 1) + m]; }
+
+// Member groups for a budget of `mib` MiB of buffer B (0: one group): runs of
+// consecutive members whose B fits the budget together, a member larger than
+// the budget alone.  Reconstruction and flux of a direction run group by
+// group, so a group's B can stay in the last-level cache between the two.
+static void batch_set_groups(hgks_ctx b, int mib) {
+  b->group_mib = mib;
+  b->group_first.assign(1, 0);
+  const int n = (int)b->members.size();
+  const size_t budget = (size_t)mib << 20;
+  size_t used = 0;
+  for (int i = 0; i < n; ++i) {
+    const size_t bytes = b->members[i]->L.nb_elems * (precision_mixed(b->cfg) ? sizeof(float) : sizeof(double));
+    if (mib > 0 && i > b->group_first.back() && used + bytes > budget) {
+      b->group_first.push_back(i);
+      used = 0;
+    }
+    used += bytes;
+  }
+  b->group_first.push_back(n);
+}
+
+template <int DIR, class R, int TX>
+static void enqueue_batch_direction(hgks_ctx b, int src_qs) {
+  const BatchTable T = b->table;
+  for (size_t g = 0; g + 1 < b->group_first.size(); ++g) {
+    const int m0 = b->group_first[g], m1 = b->group_first[g + 1];
+    const int r0 = batch_item(b, PRE_RECON + DIR, m0), r1 = batch_item(b, PRE_RECON + DIR, m1);
+    hipLaunchKernelGGL((recon_batch_kernel<DIR, R>), dim3(r1 - r0), dim3(RECON_THREADS), 0, b->stream, T, r0, r1,
+                       src_qs);
+    const int f0 = batch_item(b, flux_row<TX>(DIR), m0), f1 = batch_item(b, flux_row<TX>(DIR), m1);
+    hipLaunchKernelGGL((flux_batch_kernel<DIR, R, TX>), dim3(f1 - f0), dim3(FLUX_THREADS), 0, b->stream, T, f0, f1);
+  }
+}
 template <class R, int TX>
 static void enqueue_batch_fluxes_tx(hgks_ctx b, int src_qs) {
-  const BatchTable T = b->table;
-  hipLaunchKernelGGL((recon_batch_kernel<0, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
-  hipLaunchKernelGGL((flux_batch_kernel<0, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
-  hipLaunchKernelGGL((recon_batch_kernel<1, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
-  hipLaunchKernelGGL((flux_batch_kernel<1, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
-  hipLaunchKernelGGL((recon_batch_kernel<2, R>), dim3(b->g_recon), dim3(RECON_THREADS), 0, b->stream, T, src_qs);
-  hipLaunchKernelGGL((flux_batch_kernel<2, R, TX>), dim3(b->g_flux), dim3(FLUX_THREADS), 0, b->stream, T);
-}
-template <class R>
-static void enqueue_batch_fluxes_r(hgks_ctx b, int src_qs) {
-  if (b->tx == 64) enqueue_batch_fluxes_tx<R, 64>(b, src_qs);
-  else if (b->tx == 32) enqueue_batch_fluxes_tx<R, 32>(b, src_qs);
-  else enqueue_batch_fluxes_tx<R, 16>(b, src_qs);
+  enqueue_batch_direction<0, R, TX>(b, src_qs);
+  enqueue_batch_direction<1, R, TX>(b, src_qs);
+  enqueue_batch_direction<2, R, TX>(b, src_qs);
 }
 static void enqueue_batch_fluxes(hgks_ctx b, int src_qs) {
-  if (precision_mixed(b->cfg)) enqueue_batch_fluxes_r<float>(b, src_qs);
-  else enqueue_batch_fluxes_r<double>(b, src_qs);
+  if (precision_mixed(b->cfg)) {
+    if (b->tx == 32) enqueue_batch_fluxes_tx<float, 32>(b, src_qs);
+    else enqueue_batch_fluxes_tx<float, 16>(b, src_qs);
+  } else {
+    if (b->tx == 32) enqueue_batch_fluxes_tx<double, 32>(b, src_qs);
+    else enqueue_batch_fluxes_tx<double, 16>(b, src_qs);
+  }
 }
 // One full batched S2O4 step on the stream (also what the graph captures).
 static void enqueue_batch_step(hgks_ctx b) {
   const BatchTable T = b->table;
+  const int nc = batch_item(b, PRE_CELL, T.n);
   hipLaunchKernelGGL(begin_step_batch_kernel, dim3((T.n + 63) / 64), dim3(64), 0, b->stream, T);
   enqueue_batch_fluxes(b, 0);
-  hipLaunchKernelGGL(update_batch_kernel<1>, dim3(b->g_update), dim3(CELL_THREADS), 0, b->stream, T);
+  hipLaunchKernelGGL(update_batch_kernel<1>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
   enqueue_batch_fluxes(b, 1);
-  hipLaunchKernelGGL(update_batch_kernel<2>, dim3(b->g_update), dim3(CELL_THREADS), 0, b->stream, T);
+  hipLaunchKernelGGL(update_batch_kernel<2>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
 }
 
 // Milliseconds of `reps` runs of fn on the stream, timed with events.
@@ -1099,15 +1172,15 @@ static hgks_status time_on_stream(hgks_ctx b, Fn fn, int reps, float* ms) {
 }
 
 static std::string tune_key(hgks_ctx b) {
-  std::string k = "hgks-batch-v1 prec=" + std::to_string(b->cfg.precision) + " n=" + std::to_string(b->members.size());
+  std::string k = "hgks-batch-v2 prec=" + std::to_string(b->cfg.precision) + " n=" + std::to_string(b->members.size());
   for (hgks_ctx m : b->members)
     k += " " + std::to_string(m->cfg.n[0]) + "x" + std::to_string(m->cfg.n[1]) + "x" + std::to_string(m->cfg.n[2]);
   return k;
 }
 
-// Launch-shape autotuner: persistent grid sizes for the reconstruction, flux
-// and update kernels and the flux tile width (16, 32 or 64 faces along x),
-// timed on the ensemble's own state (these kernels write only workspace).
+// Launch-shape autotuner: the flux tile width (16 or 32 faces along x) and the
+// member-group budget for buffer B (one group, or 256, 128, 64 MiB), timed on
+// the ensemble's own state (reconstruction and flux write only workspace).
 // Results are kept in the file named by HGKS_TUNE_CACHE when set.
 static hgks_status batch_autotune(hgks_ctx b) {
   const char* path = std::getenv("HGKS_TUNE_CACHE");
@@ -1119,10 +1192,12 @@ static hgks_status batch_autotune(hgks_ctx b) {
         std::string l(line);
         const size_t tab = l.find('\t');
         if (tab == std::string::npos || l.substr(0, tab) != key) continue;
-        int tx, gr, gf, gu;
-        if (std::sscanf(l.c_str() + tab + 1, "%d %d %d %d", &tx, &gr, &gf, &gu) == 4 && gr > 0 && gf > 0 && gu > 0 &&
-            (tx == 16 || tx == 32 || tx == 64)) {
-          b->tx = tx; b->g_recon = gr; b->g_flux = gf; b->g_update = gu; b->tune_source = 2;
+        int tx, mib;
+        if (std::sscanf(l.c_str() + tab + 1, "%d %d", &tx, &mib) == 2 && (tx == 16 || tx == 32) && mib >= 0 &&
+            mib <= (1 << 20)) {
+          b->tx = tx;
+          batch_set_groups(b, mib);
+          b->tune_source = 2;
           std::fclose(f);
           return HGKS_OK;
         }
@@ -1130,70 +1205,23 @@ static hgks_status batch_autotune(hgks_ctx b) {
       std::fclose(f);
     }
   }
-  auto cands = [](int total) {
-    std::vector<int> c;
-    for (int g : {1024, 2048, 4096, 8192, 16384})
-      if (g < total) c.push_back(g);
-    c.push_back(total);  // one block per work item
-    return c;
-  };
-  const int max_recon = std::max(b->total_recon[0], std::max(b->total_recon[1], b->total_recon[2]));
   float best = 1e30f, ms = 0.0f;
-  // reconstruction grid (flux shape fixed meanwhile)
-  b->tx = 16;
-  b->g_flux = b->total_flux[0][0];
-  int best_gr = max_recon;
-  for (int g : cands(max_recon)) {
-    b->g_recon = g;
-    auto fn = [&]() {
-      const BatchTable T = b->table;
-      if (precision_mixed(b->cfg)) {
-        hipLaunchKernelGGL((recon_batch_kernel<0, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-        hipLaunchKernelGGL((recon_batch_kernel<1, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-        hipLaunchKernelGGL((recon_batch_kernel<2, float>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-      } else {
-        hipLaunchKernelGGL((recon_batch_kernel<0, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-        hipLaunchKernelGGL((recon_batch_kernel<1, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-        hipLaunchKernelGGL((recon_batch_kernel<2, double>), dim3(g), dim3(RECON_THREADS), 0, b->stream, T, 0);
-      }
-    };
-    hgks_status st = time_on_stream(b, fn, 2, &ms);
-    if (st != HGKS_OK) return st;
-    if (ms < best) { best = ms; best_gr = g; }
-  }
-  b->g_recon = best_gr;
-  // flux tile width and grid (reconstruction + flux of the three directions)
-  best = 1e30f;
-  int best_tx = 16, best_gf = b->total_flux[0][0];
-  for (int ti = 0; ti < 3; ++ti) {
-    const int tx = 16 << ti;
-    const int max_flux = std::max(b->total_flux[ti][0], std::max(b->total_flux[ti][1], b->total_flux[ti][2]));
-    for (int g : cands(max_flux)) {
+  int best_tx = 16, best_mib = 0;
+  for (int tx : {16, 32}) {
+    for (int mib : {0, 256, 128, 64}) {
       b->tx = tx;
-      b->g_flux = g;
+      batch_set_groups(b, mib);
       hgks_status st = time_on_stream(b, [&]() { enqueue_batch_fluxes(b, 0); }, 2, &ms);
       if (st != HGKS_OK) return st;
-      if (ms < best) { best = ms; best_tx = tx; best_gf = g; }
+      if (ms < best) { best = ms; best_tx = tx; best_mib = mib; }
     }
   }
   b->tx = best_tx;
-  b->g_flux = best_gf;
-  // update grid (stage 1 writes only workspace)
-  best = 1e30f;
-  int best_gu = b->total_cells;
-  for (int g : cands(b->total_cells)) {
-    auto fn = [&]() {
-      hipLaunchKernelGGL(update_batch_kernel<1>, dim3(g), dim3(CELL_THREADS), 0, b->stream, b->table);
-    };
-    hgks_status st = time_on_stream(b, fn, 3, &ms);
-    if (st != HGKS_OK) return st;
-    if (ms < best) { best = ms; best_gu = g; }
-  }
-  b->g_update = best_gu;
+  batch_set_groups(b, best_mib);
   b->tune_source = 1;
   if (path) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s\t%d %d %d %d\n", key.c_str(), b->tx, b->g_recon, b->g_flux, b->g_update);
+      std::fprintf(f, "%s\t%d %d\n", key.c_str(), b->tx, b->group_mib);
       std::fclose(f);
     }
   }
@@ -1432,7 +1460,10 @@ hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t
     if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
     total += align256(make_layout(cfgs[i]).total);
   }
-  *bytes = total + batch_table_bytes(n);
+  const std::vector<int> pre = batch_prefix(n, cfgs);
+  if (pre.empty()) return HGKS_E_INVALID;
+  int off[PRE_ROWS];
+  *bytes = total + batch_table_bytes(n, batch_coarse(n, pre, off).size());
   return HGKS_OK;
 }
 
@@ -1456,7 +1487,6 @@ hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q
   char* base = static_cast<char*>(ws_dev);
   size_t off = 0;
   std::vector<BatchEntry> host(n);
-  std::vector<int> pre((size_t)PRE_ROWS * (n + 1), 0);
   for (int i = 0; i < n; ++i) {
     const size_t sz = align256(make_layout(cfgs[i]).total);
     hgks_ctx m = nullptr;
@@ -1478,29 +1508,21 @@ hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q
     e.sc = m->sc;
     e.qref = m->qref;
     e.cfl = cfgs[i].cfl;
-    const int rec[3] = {recon_tiles<0>(m->P), recon_tiles<1>(m->P), recon_tiles<2>(m->P)};
-    for (int d = 0; d < 3; ++d) {
-      pre[(size_t)(PRE_RECON + d) * (n + 1) + i + 1] = pre[(size_t)(PRE_RECON + d) * (n + 1) + i] + rec[d];
-      const int fl[3] = {flux_tiles<16>(m->P, d), flux_tiles<32>(m->P, d), flux_tiles<64>(m->P, d)};
-      for (int t = 0; t < 3; ++t) {
-        const size_t row = (size_t)(PRE_FLUX + 3 * t + d) * (n + 1);
-        pre[row + i + 1] = pre[row + i] + fl[t];
-      }
-    }
-    pre[(size_t)PRE_CELL * (n + 1) + i + 1] = pre[(size_t)PRE_CELL * (n + 1) + i] + (int)cell_blocks(m->P);
   }
-  for (int d = 0; d < 3; ++d) {
-    b->total_recon[d] = pre[(size_t)(PRE_RECON + d) * (n + 1) + n];
-    for (int t = 0; t < 3; ++t) b->total_flux[t][d] = pre[(size_t)(PRE_FLUX + 3 * t + d) * (n + 1) + n];
-  }
-  b->total_cells = pre[(size_t)PRE_CELL * (n + 1) + n];
+  b->pre = batch_prefix(n, cfgs);
+  const std::vector<int> coarse = batch_coarse(n, b->pre, b->table.coarse_off);
   BatchEntry* dE = reinterpret_cast<BatchEntry*>(base + off);
-  int* dpre = reinterpret_cast<int*>(base + off + align256((size_t)n * sizeof(BatchEntry)));
+  off += align256((size_t)n * sizeof(BatchEntry));
+  int* dpre = reinterpret_cast<int*>(base + off);
+  off += align256(b->pre.size() * sizeof(int));
+  int* dcoarse = reinterpret_cast<int*>(base + off);
   HIP_TRY(b, hipMemcpyAsync(dE, host.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(b, hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipMemcpyAsync(dpre, b->pre.data(), b->pre.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipMemcpyAsync(dcoarse, coarse.data(), coarse.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(b, hipStreamSynchronize(b->stream));
   b->table.E = dE;
   b->table.pre = dpre;
+  b->table.coarse = dcoarse;
   b->table.n = n;
   hgks_status st = batch_autotune(b);
   if (st != HGKS_OK) {
@@ -1534,14 +1556,16 @@ hgks_status hgks_batch_stats(hgks_ctx ctx, int32_t i, hgks_stats_t* out) {
 
 hgks_status hgks_batch_info(hgks_ctx ctx, int64_t info[8]) {
   if (!ctx || !info || ctx->members.empty()) return HGKS_E_INVALID;
-  info[0] = (int64_t)ctx->members.size();
+  const int n = (int)ctx->members.size();
+  const int fr = ctx->tx == 32 ? flux_row<32>(0) : flux_row<16>(0);
+  info[0] = n;
   info[1] = ctx->tx;
-  info[2] = ctx->g_recon;
-  info[3] = ctx->g_flux;
-  info[4] = ctx->g_update;
+  info[2] = ctx->group_mib;
+  info[3] = (int64_t)ctx->group_first.size() - 1;
+  info[4] = (int64_t)batch_item(ctx, fr, n) + batch_item(ctx, fr + 1, n) + batch_item(ctx, fr + 2, n);
   info[5] = ctx->tune_source;
-  info[6] = (int64_t)ctx->total_recon[0] + ctx->total_recon[1] + ctx->total_recon[2];
-  info[7] = ctx->total_cells;
+  info[6] = (int64_t)batch_item(ctx, PRE_RECON, n) + batch_item(ctx, PRE_RECON + 1, n) + batch_item(ctx, PRE_RECON + 2, n);
+  info[7] = batch_item(ctx, PRE_CELL, n);
   return HGKS_OK;
 }
 

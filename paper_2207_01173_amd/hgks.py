@@ -231,7 +231,7 @@ def hgks_batch_stats(ctx, i: int) -> dict:
     }
 
 
-BATCH_INFO_KEYS = ("instances", "flux_tile_x", "grid_recon", "grid_flux", "grid_update", "tune_source",
+BATCH_INFO_KEYS = ("instances", "flux_tile_x", "group_mib", "groups", "flux_tiles", "tune_source",
                    "recon_tiles", "cell_blocks")
 
 

@@ -48,7 +48,8 @@ def test_batch_members_equal_standalone_runs(hg, tmp_path, precision):
     b = hg.Batch([p for p, _ in ens], [q for _, q in ens], precision=prec)
     info = b.info()
     say("batch info", info)
-    assert info["instances"] == len(ens) and info["flux_tile_x"] in (16, 32, 64) and info["tune_source"] == 1
+    assert info["instances"] == len(ens) and info["flux_tile_x"] in (16, 32) and info["tune_source"] == 1
+    assert info["group_mib"] in (0, 64, 128, 256) and 1 <= info["groups"] <= len(ens)
     b.step(3)
     for i, (p, q0) in enumerate(ens):
         s = hg.Solver(p, q0, precision=prec)
@@ -65,7 +66,7 @@ def test_batch_members_equal_standalone_runs(hg, tmp_path, precision):
     # the same ensemble again reads the tuned shapes from the cache file
     b2 = hg.Batch([p for p, _ in ens], [q for _, q in ens], precision=prec)
     assert b2.info()["tune_source"] == 2
-    for k in ("flux_tile_x", "grid_recon", "grid_flux", "grid_update"):
+    for k in ("flux_tile_x", "group_mib", "groups", "flux_tiles"):
         assert b2.info()[k] == info[k]
     b2.close()
     del os.environ["HGKS_TUNE_CACHE"]
