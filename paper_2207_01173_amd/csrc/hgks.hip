@@ -339,14 +339,18 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   // ---- second tangential sweep along t2 ----------------------------------
   const size_t NB = (size_t)be[0] * be[1] * be[2];
   const size_t qstride = 2 * NB;
-  size_t bi[5];
+  // Lane byte offsets within one quantity's two Gauss lines (below 2^32:
+  // checked when the configuration is validated), added to a per-quantity base
+  // that is uniform across the block, so loads take the scalar-base form.
+  uint32_t bi[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     int b[3] = {f[0], f[1], f[2]};
     int t = f[D2] + j - 2;
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
-    bi[j] = (size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0]);
+    bi[j] = (uint32_t)(sizeof(R) *
+                       ((size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0])));
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
@@ -369,9 +373,17 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.pr_fix = R(P.pr_fix);
   // Five stencil values of quantity qi along t2.
   auto stencil = [&](int qi, R v[5]) {
+    const HGKS_GLOBAL char* base = reinterpret_cast<const HGKS_GLOBAL char*>(Bg + (size_t)qi * qstride);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = Bg[qi * qstride + bi[j]];
+    for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(base + bi[j]);
   };
+
+  // Raw t2 stencils of a phase's inputs.  On the FP64 path (one wave per SIMD,
+  // so nothing else hides memory latency) each phase issues the loads of the
+  // next phase before its own arithmetic; on the FP32 path the registers that
+  // takes would cost a wave of occupancy, so each phase loads its own.
+  constexpr bool kPrefetch = sizeof(R) == 8;
+  R pa[5][5], pb[5][5];
 
   // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
   R ql[5], qr[5], tl2[5], tr2[5];
@@ -387,6 +399,13 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     qr[k] = R(double(val) + rl[k]);
     tr2[k] = der * st2;
   }
+  if (kPrefetch) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      stencil(B_DLN + k, pa[k]);
+      stencil(B_DLT1 + k, pb[k]);
+    }
+  }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
   __builtin_amdgcn_sched_barrier(0);
@@ -396,12 +415,20 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      R v[5];
-      stencil(B_DLN + k, v);
-      dq[0][k] = gauss_value(v, gp) * sn;
-      stencil(B_DLT1 + k, v);
-      dq[1][k] = gauss_value(v, gp) * st1;
+      if (!kPrefetch) {
+        stencil(B_DLN + k, pa[k]);
+        stencil(B_DLT1 + k, pb[k]);
+      }
+      dq[0][k] = gauss_value(pa[k], gp) * sn;
+      dq[1][k] = gauss_value(pb[k], gp) * st1;
       dq[2][k] = tl2[k];
+    }
+    if (kPrefetch) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        stencil(B_DRN + k, pa[k]);
+        stencil(B_DRT1 + k, pb[k]);
+      }
     }
     flux_side<R, true>(ql, dq, g, acc);
   }
@@ -412,12 +439,17 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      R v[5];
-      stencil(B_DRN + k, v);
-      dq[0][k] = gauss_value(v, gp) * sn;
-      stencil(B_DRT1 + k, v);
-      dq[1][k] = gauss_value(v, gp) * st1;
+      if (!kPrefetch) {
+        stencil(B_DRN + k, pa[k]);
+        stencil(B_DRT1 + k, pb[k]);
+      }
+      dq[0][k] = gauss_value(pa[k], gp) * sn;
+      dq[1][k] = gauss_value(pb[k], gp) * st1;
       dq[2][k] = tr2[k];
+    }
+    if (kPrefetch) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) stencil(B_D0 + k, pa[k]);
     }
     flux_side<R, false>(qr, dq, g, acc);
   }
@@ -429,9 +461,8 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq0n[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      R v[5];
-      stencil(B_D0 + k, v);
-      dq0n[k] = gauss_linear(v, gp) * sn;
+      if (!kPrefetch) stencil(B_D0 + k, pa[k]);
+      dq0n[k] = gauss_linear(pa[k], gp) * sn;
     }
     flux_finish(dq0n, g, acc, F1, F2);
   }
@@ -987,6 +1018,17 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
     if (c->bc[a] == HGKS_BC_ISOTHERMAL_WALL && a != 1) return bad("walls are supported on the y axis only");
   }
   if ((size_t)c->n[0] * c->n[1] * c->n[2] > ((size_t)1 << 34)) return bad("grid too large");
+  {
+    // the flux kernel addresses the two Gauss lines of one quantity of buffer B
+    // with 32-bit byte offsets
+    Params P{};
+    for (int a = 0; a < 3; ++a) { P.n[a] = c->n[a]; P.bc[a] = c->bc[a]; }
+    for (int d = 0; d < 3; ++d) {
+      int be[3], bo[3];
+      b_extents(P, d, be, bo);
+      if (2 * sizeof(double) * be[0] * be[1] * be[2] >= ((size_t)1 << 32)) return bad("grid too large");
+    }
+  }
   if (!(c->gamma > 1.0 && c->gamma <= 5.0 / 3.0)) return bad("gamma out of (1, 5/3]");
   if (!(c->prandtl > 0.0)) return bad("prandtl must be > 0");
   if (!(c->mu_ref >= 0.0)) return bad("mu_ref must be >= 0");
