@@ -367,8 +367,10 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   GasParams<R> g;
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
+  g.K3 = R(P.K + 3.0);
+  g.iK3 = R(1.0 / (P.K + 3.0));
   g.mu_ref = R(P.mu_ref);
-  g.T_ref = R(P.T_ref);
+  g.iT_ref = R(P.T_ref > 0.0 ? 1.0 / P.T_ref : 0.0);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
   // Five stencil values of quantity qi along t2.
@@ -480,13 +482,14 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
   if (!valid || gpi != 0) return;  // this lane only
   const double area = gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
+  const double idt = 1.0 / dt, idt2 = 4.0 * idt * idt;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     double I1 = 0.25 * area * s1[k];  // integral over [0, dt]
     double I2 = 0.25 * area * s2[k];  // integral over [0, dt/2]
-    loc[k] = (4.0 * I2 - I1) / dt;
-    loc[5 + k] = 4.0 * (I1 - 2.0 * I2) / (dt * dt);
+    loc[k] = (4.0 * I2 - I1) * idt;
+    loc[5 + k] = (I1 - 2.0 * I2) * idt2;
   }
   const size_t NF = (size_t)fe[0] * fe[1] * fe[2];
   const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fe[0] + f[0];

@@ -24,7 +24,8 @@ template <> __device__ __forceinline__ double pos_rcp<double>(double x) {
   r = fma(fma(-x, r, 1.0), r, r);
   return r;
 }
-template <> __device__ __forceinline__ float pos_rcp<float>(float x) { return 1.0f / x; }
+// FP32 (mixed path): the hardware reciprocal, within 1 ulp.
+template <> __device__ __forceinline__ float pos_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // The three quadratic candidates through averages (v0,v1,v2), (v1,v2,v3),
 // (v2,v3,v4), written about the centre cell (x in [-1/2, 1/2]) as
@@ -64,9 +65,9 @@ __device__ __forceinline__ void wz_weights(const R beta[3], R d0, R d1, R d2, R 
     a1 = d1 * (b1 + t5) * (b0 * b2);
     a2 = d2 * (b2 + t5) * (b0 * b1);
   } else {
-    a0 = d0 * (R(1) + t5 / b0);
-    a1 = d1 * (R(1) + t5 / b1);
-    a2 = d2 * (R(1) + t5 / b2);
+    a0 = d0 * (R(1) + t5 * pos_rcp(b0));
+    a1 = d1 * (R(1) + t5 * pos_rcp(b1));
+    a2 = d2 * (R(1) + t5 * pos_rcp(b2));
   }
   const R inv = pos_rcp(a0 + a1 + a2);
   w[0] = a0 * inv;
@@ -165,15 +166,16 @@ __device__ __forceinline__ void normal_sweep(const R c[6], R& ql, R& qr, R& dl, 
 template <class R> struct State { R rho, U, V, W, lam; };
 
 template <class R>
-__device__ __forceinline__ State<R> primitive(const R q[5], R gm1) {
+__device__ __forceinline__ State<R> primitive(const R q[5], R gm1, R& ir, R& ihl) {
   State<R> s;
   s.rho = q[0];
-  R ir = R(1) / q[0];
+  ir = pos_rcp(q[0]);
   s.U = q[1] * ir;
   s.V = q[2] * ir;
   s.W = q[3] * ir;
-  R p = gm1 * (q[4] - R(0.5) * (q[1] * s.U + q[2] * s.V + q[3] * s.W));
-  s.lam = R(0.5) * q[0] / p;
+  const R p = gm1 * (q[4] - R(0.5) * (q[1] * s.U + q[2] * s.V + q[3] * s.W));
+  s.lam = R(0.5) * q[0] * pos_rcp(p);
+  ihl = p * ir;  // 1/(2 lambda) = p/rho
   return s;
 }
 
@@ -191,7 +193,7 @@ __device__ __forceinline__ void chain(R mean, R ihl, R m0, R m1, R o[N]) {
 template <class R, int SIDE>
 __device__ __forceinline__ void half_moments01(const State<R>& s, R& m0, R& m1) {
   R sl = sqrt(s.lam);
-  R e = exp(-s.lam * s.U * s.U) * R(0.28209479177387814347) / sl;  // e^{-l U^2} / (2 sqrt(pi l))
+  R e = exp(-s.lam * s.U * s.U) * R(0.28209479177387814347) * pos_rcp(sl);  // e^{-l U^2} / (2 sqrt(pi l))
   m0 = R(0.5) * erfc(-R(SIDE) * sl * s.U);
   m1 = s.U * m0 + R(SIDE) * e;
 }
@@ -310,14 +312,14 @@ __device__ __forceinline__ void series_pi(const R a[3][5], const VW<R>& e, Quad<
 
 // Closed-form solution of <(a . psi) psi> = b for a Maxwellian state.
 template <class R>
-__device__ __forceinline__ void slope_solve(const State<R>& s, R ihl, R K, const R b[5], R a[5]) {
-  R q2 = s.U * s.U + s.V * s.V + s.W * s.W + (K + R(3)) * ihl;
+__device__ __forceinline__ void slope_solve(const State<R>& s, R ihl, R K3, R iK3, const R b[5], R a[5]) {
+  R q2 = s.U * s.U + s.V * s.V + s.W * s.W + K3 * ihl;
   R r2 = b[1] - s.U * b[0];
   R r3 = b[2] - s.V * b[0];
   R r4 = b[3] - s.W * b[0];
   R r5 = R(2) * b[4] - q2 * b[0];
   R tl = R(2) * s.lam;
-  a[4] = tl * tl / (K + R(3)) * (r5 - R(2) * (s.U * r2 + s.V * r3 + s.W * r4));
+  a[4] = tl * tl * iK3 * (r5 - R(2) * (s.U * r2 + s.V * r3 + s.W * r4));
   a[3] = tl * r4 - s.W * a[4];
   a[2] = tl * r3 - s.V * a[4];
   a[1] = tl * r2 - s.U * a[4];
@@ -329,17 +331,18 @@ __device__ __forceinline__ void slope_solve(const State<R>& s, R ihl, R K, const
 // ---------------------------------------------------------------------------
 
 template <class R> struct GasParams {
-  R gm1;      // gamma - 1
-  R K;        // internal degrees of freedom
-  R mu_ref, T_ref, mu_exp;
-  R pr_fix;   // 1/Pr - 1
+  R gm1;       // gamma - 1
+  R K;         // internal degrees of freedom
+  R K3, iK3;   // K + 3 and its reciprocal
+  R mu_ref, iT_ref, mu_exp;
+  R pr_fix;    // 1/Pr - 1
 };
 
 // Integrals over [0, delta] of the six time factors of the BGK solution.
 template <class R>
-__device__ __forceinline__ void time_integrals(R tau, R delta, R C[6]) {
+__device__ __forceinline__ void time_integrals(R tau, R itau, R delta, R C[6]) {
   if (tau > R(0)) {
-    R eta = exp(-delta / tau);
+    R eta = exp(-delta * itau);
     R om = R(1) - eta;
     R t2 = tau * tau;
     C[0] = delta - tau * om;
@@ -380,10 +383,10 @@ template <class R>
 __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const GasParams<R>& g, R dt, FluxAcc<R>& A) {
   R q0[5];
   {
-    const State<R> sl = primitive(ql, g.gm1), sr = primitive(qr, g.gm1);
+    R irl, irr, il, ir;
+    const State<R> sl = primitive(ql, g.gm1, irl, il), sr = primitive(qr, g.gm1, irr, ir);
     half_moments01<R, 1>(sl, A.lm0, A.lm1);
     half_moments01<R, -1>(sr, A.rm0, A.rm1);
-    const R il = R(0.5) / sl.lam, ir = R(0.5) / sr.lam;
     // <psi> with half-space u: (m0, m1, V m0, W m0, (m2 + m0 (V^2 + W^2 + (K + 2) ihl)) / 2)
     const R l2 = sl.U * A.lm1 + il * A.lm0, r2 = sr.U * A.rm1 + ir * A.rm0;
     const R lt = sl.V * sl.V + sl.W * sl.W + (g.K + R(2)) * il;
@@ -394,15 +397,16 @@ __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const G
     q0[3] = sl.rho * sl.W * A.lm0 + sr.rho * sr.W * A.rm0;
     q0[4] = R(0.5) * (sl.rho * (l2 + A.lm0 * lt) + sr.rho * (r2 + A.rm0 * rt));
   }
-  A.s0 = primitive(q0, g.gm1);
-  A.ihl0 = R(0.5) / A.s0.lam;
+  R ir0;
+  A.s0 = primitive(q0, g.gm1, ir0, A.ihl0);
   // collision time tau = mu(T0) / p0, T0 = p0/rho0 = 1/(2 lambda0)
   const R p0 = A.s0.rho * A.ihl0;
   R mu = g.mu_ref;
-  if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 / g.T_ref, g.mu_exp);
-  const R tau = mu / p0;
-  time_integrals(tau, dt, A.C1);
-  time_integrals(tau, R(0.5) * dt, A.C2);
+  if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 * g.iT_ref, g.mu_exp);
+  const R tau = mu * pos_rcp(p0);
+  const R itau = tau > R(0) ? pos_rcp(tau) : R(0);
+  time_integrals(tau, itau, dt, A.C1);
+  time_integrals(tau, itau, R(0.5) * dt, A.C2);
   A.hu2 = R(0.5) * (A.s0.U * A.s0.U + A.s0.V * A.s0.V + A.s0.W * A.s0.W);
 #pragma unroll
   for (int k = 0; k < 5; ++k) { A.F1[k] = R(0); A.F2[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
@@ -416,18 +420,17 @@ __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const G
 // part of the tangential slopes of Q0.
 template <class R, bool LEFT>
 __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const GasParams<R>& g, FluxAcc<R>& Acc) {
-  State<R> s = primitive(q, g.gm1);
-  const R ihl = R(0.5) / s.lam;
+  R ir, ihl;
+  State<R> s = primitive(q, g.gm1, ir, ihl);
   VW<R> e;
   vw_moments(s, ihl, g.K, e);
   R a[3][5];
-  const R ir = R(1) / s.rho;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     R b[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = dq[d][k] * ir;
-    slope_solve(s, ihl, g.K, b, a[d]);
+    slope_solve(s, ihl, g.K3, g.iK3, b, a[d]);
   }
   Quad<R> pi[4];
   series_pi(a, e, pi);
@@ -438,7 +441,7 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
     assemble<R, 0, 4>(pi, Mf, T);
 #pragma unroll
     for (int k = 0; k < 5; ++k) T[k] = -T[k];
-    slope_solve(s, ihl, g.K, T, A);
+    slope_solve(s, ihl, g.K3, g.iK3, T, A);
   }
   R Mh[7];
   if (LEFT) chain<R, 7>(s.U, ihl, Acc.lm0, Acc.lm1, Mh);
@@ -494,18 +497,18 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
   R Mf[7];
   chain<R, 7>(s0.U, ihl0, R(1), s0.U, Mf);
   R a[3][5];
-  const R ir = R(1) / s0.rho;
+  const R ir = pos_rcp(s0.rho);
   {
     R b[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = dq0n[k] * ir;
-    slope_solve(s0, ihl0, g.K, b, a[0]);
+    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[0]);
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[0][k] * ir;
-    slope_solve(s0, ihl0, g.K, b, a[1]);
+    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[1]);
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[1][k] * ir;
-    slope_solve(s0, ihl0, g.K, b, a[2]);
+    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[2]);
   }
   Quad<R> pi[4];
   series_pi(a, e, pi);
@@ -516,7 +519,7 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
     R b[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = -T[k];
-    slope_solve(s0, ihl0, g.K, b, A);
+    slope_solve(s0, ihl0, g.K3, g.iK3, b, A);
   }
   const Quad<R> unit[1] = {quad_c(R(1), e)};
   Quad<R> qa[3];
