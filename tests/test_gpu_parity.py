@@ -56,6 +56,51 @@ def test_residual_parity(hg, oracle, n, seed):
     s.close()
 
 
+def load_samples(name):
+    """A sampled-oracle fixture: header values and rows (iz, iy, ix, Q)."""
+    import os
+
+    head, rows = {}, []
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.startswith("# ") and len(line.split()) >= 3 and line.split()[1] in (
+                    "steps", "dt_last", "Ek", "eps_com", "maxabs"):
+                parts = line.split()
+                head[parts[1]] = [float(v) for v in parts[2:]]
+            elif line.strip() and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return head, np.array(rows)
+
+
+def test_tgv128_ten_steps_sampled(hg):
+    """TGV 128^3 (Ma 0.1, Re 1600, Pr 0.72), 10 CFL-0.5 steps, FP64, against
+    the oracle's state at 512 seeded cells (tests/golden/tgv128_oracle_samples.txt,
+    written by its make_ script from the oracle alone): relative error per
+    component (against the component's max |Q|) <= 1e-11, time step to
+    1e-12.  The statistics are sums over N = 128^3 cells, taken in a
+    different order on the two sides (the oracle adds sequentially, the GPU
+    in a fixed tree): recursive summation of N terms of one sign is exact to
+    (N - 1) u relative (u = 2^-53), which bounds their agreement."""
+    head, rows = load_samples("tgv128_oracle_samples.txt")
+    p = W.tgv_params(128, ma=0.1, re=1600.0, pr=0.72, cfl=0.5)
+    say("tgv128 10 CFL steps vs sampled oracle")
+    s = hg.Solver(p, W.tgv_initial(p))
+    s.step(int(head["steps"][0]), 0.0)
+    got = s.state()
+    st = s.stats()
+    s.close()
+    iz, iy, ix = (rows[:, k].astype(int) for k in range(3))
+    ref = rows[:, 3:].T
+    err = np.abs(got[:, iz, iy, ix] - ref).max(axis=1) / np.array(head["maxabs"])
+    say("  sampled state err", err, "dt", st["dt_last"], head["dt_last"][0])
+    assert (err <= 1e-11).all(), err
+    assert abs(st["dt_last"] - head["dt_last"][0]) <= 1e-12 * head["dt_last"][0]
+    sum_tol = max(1e-11, (128 ** 3 - 1) * 2.0 ** -53)
+    for key in ("Ek", "eps_com"):
+        say(f"  {key}: gpu {st[key]!r} oracle {head[key][0]!r}")
+        assert abs(st[key] - head[key][0]) <= sum_tol * abs(head[key][0]), (key, st[key], head[key][0])
+
+
 def test_tgv32_ten_steps(hg, oracle):
     """P16: TGV 32^3 (Ma 0.1, Re 1600, Pr 0.72), 10 steps at the CFL-0.5 time
     step of the initial state, FP64: relative max-norm error <= 1e-11."""
