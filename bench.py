@@ -136,6 +136,154 @@ def ensemble_bench(steps: int, precision: str) -> dict:
     }
 
 
+def tgv_history(n: int, ma: float, t_end: float, every: int) -> dict:
+    """TGV at n^3 (Re 1600, Pr 0.72, CFL 0.5) advanced to t_end by the FP64
+    and the mixed path in lockstep, the mixed path on the FP64 run's time
+    steps so the two are compared at matched steps: E_k and eps_com every
+    `every` steps, and the mixed-minus-FP64 state max-norm when t first
+    reaches 1, 2, 5 and 10."""
+    import torch
+
+    from paper_2207_01173_amd import hgks
+    from paper_2207_01173_amd import workloads as W
+
+    p = W.tgv_params(n, ma=ma, re=1600.0, pr=0.72, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    s64 = hgks.Solver(p, q0, precision=hgks.FP64)
+    smx = hgks.Solver(p, q0, precision=hgks.MIXED)
+    keys = ("step", "t", "Ek_fp64", "eps_com_fp64", "Ek_mixed", "eps_com_mixed")
+    hist = {k: [] for k in keys}
+    marks = [m for m in (1.0, 2.0, 5.0, 10.0) if m <= t_end]
+    at_marks = []
+
+    def record(step, st64, stmx):
+        for k, v in zip(keys, (step, st64["t"], st64["Ek"], st64["eps_com"], stmx["Ek"], stmx["eps_com"])):
+            hist[k].append(v)
+
+    record(0, s64.stats(), smx.stats())
+    step, t = 0, 0.0
+    w0 = time.perf_counter()
+    while t < t_end:
+        s64.step(1, 0.0)
+        st64 = s64.stats()
+        smx.step(1, st64["dt_last"])
+        step += 1
+        t = st64["t"]
+        hit = bool(marks) and t >= marks[0]
+        if step % every == 0 or hit or t >= t_end:
+            stmx = smx.stats()
+            record(step, st64, stmx)
+        if hit:
+            a, b = s64.q, smx.q
+            rel = ((b - a).abs().amax(dim=(1, 2, 3)) / a.abs().amax(dim=(1, 2, 3))).tolist()
+            mom = float((b[1:4] - a[1:4]).abs().max() / a[1:4].pow(2).sum(dim=0).sqrt().max())
+            at_marks.append({"t_mark": marks.pop(0), "t": t, "step": step, "state_rel_maxnorm": rel,
+                             "momentum_rel_to_max_speed": mom,
+                             "Ek_rel": abs(stmx["Ek"] - st64["Ek"]) / st64["Ek"],
+                             "eps_com_rel": abs(stmx["eps_com"] - st64["eps_com"]) / st64["eps_com"]})
+            print(f"# t={t:.4f} step {step}: mixed-fp64 state rel max-norm {rel}", file=sys.stderr, flush=True)
+        if step % 500 == 0:
+            print(f"# step {step} t={t:.4f} E_k={st64['Ek']:.6e} ({time.perf_counter() - w0:.0f} s)",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    s64.close()
+    smx.close()
+    return {"metric": f"TGV {n}^3 E_k and eps_com histories, FP64 and mixed at matched steps",
+            "n": n, "ma": ma, "re": 1600.0, "steps": step, "t_end": t, "every": every,
+            "wall_s": wall, "mixed_vs_fp64": at_marks, "history": hist}
+
+
+def channel_run(n: int, t_end: float, every: int) -> dict:
+    """Turbulent channel (2 pi x 2 x pi, n^3, tanh-stretched y, isothermal
+    walls, Ma_b 0.5, Re_b 3000, constant body force, Poiseuille + 10% noise)
+    advanced to t_end by the FP64 and the mixed path in lockstep (the mixed
+    path on the FP64 run's time steps).  Every `every` steps: wall shear stress
+    on both walls and bulk velocity from x-z plane means; at the end the mean
+    U(y) and T(y) of both paths and their state max-norm difference."""
+    import numpy as np
+    import torch
+
+    from paper_2207_01173_amd import hgks
+    from paper_2207_01173_amd import workloads as W
+
+    p = W.channel_params((n, n, n), ma_b=0.5, re_b=3000.0)
+    q0 = W.channel_initial(p, seed=2207)
+    y = torch.as_tensor(W.channel_y_centres(p), dtype=torch.float64, device="cuda")
+    ylo, yhi = p["lo"][1], p["hi"][1]
+    edges = torch.as_tensor(np.concatenate(([ylo], 0.5 * (W.channel_y_centres(p)[1:] + W.channel_y_centres(p)[:-1]),
+                                            [yhi])), dtype=torch.float64, device="cuda")
+    dy = edges[1:] - edges[:-1]
+    mu_w = p["mu_ref"]  # mu at T = T_w
+    gm1 = p["gamma"] - 1.0
+
+    def means(q):
+        rho = q[0].mean(dim=(0, 2))
+        U = (q[1] / q[0]).mean(dim=(0, 2))
+        ke = 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
+        T = (gm1 * (q[4] - ke) / q[0]).mean(dim=(0, 2))
+        return rho, U, T
+
+    def wall_shear(U):
+        # dU/dy at each wall from the first two cell centres and U = 0 at the wall
+        # (one-sided quadratic through the wall point)
+        out = []
+        for i0, i1, yw in ((0, 1, ylo), (n - 1, n - 2, yhi)):
+            d1, d2 = abs(float(y[i0]) - yw), abs(float(y[i1]) - yw)
+            u1, u2 = float(U[i0]), float(U[i1])
+            out.append(mu_w * (u1 * d2 * d2 - u2 * d1 * d1) / (d1 * d2 * (d2 - d1)))
+        return out
+
+    def bulk(q):
+        rho_u = q[1].mean(dim=(0, 2))
+        rho = q[0].mean(dim=(0, 2))
+        return float((rho_u * dy).sum() / (rho * dy).sum())
+
+    s64 = hgks.Solver(p, q0, precision=hgks.FP64)
+    smx = hgks.Solver(p, q0, precision=hgks.MIXED)
+    hist = {k: [] for k in ("step", "t", "tau_w_fp64", "tau_w_mixed", "U_b_fp64", "U_b_mixed")}
+
+    def record(step, t):
+        _, U64, _ = means(s64.q)
+        _, Umx, _ = means(smx.q)
+        for k, v in (("step", step), ("t", t), ("tau_w_fp64", wall_shear(U64)), ("tau_w_mixed", wall_shear(Umx)),
+                     ("U_b_fp64", bulk(s64.q)), ("U_b_mixed", bulk(smx.q))):
+            hist[k].append(v)
+        print(f"# step {step} t={t:.4f} tau_w fp64 {hist['tau_w_fp64'][-1]} mixed {hist['tau_w_mixed'][-1]} "
+              f"U_b {hist['U_b_fp64'][-1]:.6f} {hist['U_b_mixed'][-1]:.6f} ({time.perf_counter() - w0:.0f} s)",
+              file=sys.stderr, flush=True)
+
+    w0 = time.perf_counter()
+    record(0, 0.0)
+    step, t = 0, 0.0
+    while t < t_end:
+        s64.step(1, 0.0)
+        st64 = s64.stats()
+        if st64["nonfinite"] or not (st64["min_p"] > 0):
+            raise RuntimeError(f"channel FP64 state invalid at step {step}")
+        smx.step(1, st64["dt_last"])
+        step += 1
+        t = st64["t"]
+        if step % every == 0 or t >= t_end:
+            record(step, t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    rho64, U64, T64 = means(s64.q)
+    rhomx, Umx, Tmx = means(smx.q)
+    a, b = s64.q, smx.q
+    rel = ((b - a).abs().amax(dim=(1, 2, 3)) / a.abs().amax(dim=(1, 2, 3))).tolist()
+    stmx = smx.stats()
+    s64.close()
+    smx.close()
+    return {"metric": f"channel {n}^3 (Ma_b 0.5, Re_b 3000): wall shear and mean profiles, FP64 and mixed",
+            "n": n, "steps": step, "t_end": t, "wall_s": wall, "every": every,
+            "mixed_nonfinite": stmx["nonfinite"], "mixed_vs_fp64_state_rel_maxnorm": rel,
+            "profiles": {"y": y.tolist(), "U_fp64": U64.tolist(), "U_mixed": Umx.tolist(),
+                         "T_fp64": T64.tolist(), "T_mixed": Tmx.tolist(),
+                         "rho_fp64": rho64.tolist(), "rho_mixed": rhomx.tolist()},
+            "history": hist}
+
+
 def tgv_workload(n: int):
     from paper_2207_01173_amd import workloads as W
 
@@ -169,8 +317,8 @@ def cpu_baseline(n_sample: int = 64, steps: int = 1) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -178,6 +326,12 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--ensemble", action="store_true",
                     help="measure the 64-instance ensemble (batched vs per-instance loop) instead")
+    ap.add_argument("--history", type=float, default=0.0, metavar="T_END",
+                    help="instead: TGV --n^3 at Ma --ma to t = T_END, FP64 and mixed histories")
+    ap.add_argument("--channel", type=float, default=0.0, metavar="T_END",
+                    help="instead: channel at --n^3 to t = T_END, FP64 and mixed wall shear and profiles")
+    ap.add_argument("--ma", type=float, default=0.1, help="Mach number of --history")
+    ap.add_argument("--every", type=int, default=10, help="statistics interval of --history (steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -198,6 +352,12 @@ def main() -> int:
         return copy_calibration(args.copy_calibration)
     if args.ensemble:
         print(json.dumps(ensemble_bench(args.steps, args.precision)), flush=True)
+        return 0
+    if args.channel > 0:
+        print(json.dumps(channel_run(args.n, args.channel, args.every)), flush=True)
+        return 0
+    if args.history > 0:
+        print(json.dumps(tgv_history(args.n, args.ma, args.history, args.every)), flush=True)
         return 0
     n = args.n
     p = tgv_workload(n)
