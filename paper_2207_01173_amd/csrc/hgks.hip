@@ -236,8 +236,11 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   }
   __syncthreads();
 
-  // ---- first tangential sweep: one (face, Gauss line) per thread --------
-  const int o = threadIdx.x & 127, g1 = threadIdx.x >> 7;
+  // ---- first tangential sweep: both Gauss lines of one face per thread -----
+  // Waves 0-1 (h = 0) take the left-state quantities, waves 2-3 (h = 1) the
+  // right-state ones; the two Gauss lines share each stencil's candidates and
+  // WENO-Z factors.  The linear equilibrium slopes split 3 + 2 components.
+  const int o = threadIdx.x & 127, h = threadIdx.x >> 7;
   int lo[3];
   lo[0] = o % S[0];
   lo[1] = (o / S[0]) % S[1];
@@ -255,31 +258,35 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   }
   const size_t NB = (size_t)be[0] * be[1] * be[2];
   const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * be[0] + (f[0] - bo[0]);
-  HGKS_GLOBAL R* out = gmem(B) + (size_t)g1 * NB + bidx;
+  HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
   const size_t qstride = 2 * NB;
-  GaussPoint<R> gp(g1);
+  auto put = [&](int q, const R val[2]) {
+    out[q * qstride] = val[0];
+    out[q * qstride + NB] = val[1];
+  };
+  auto stencil = [&](int row, R v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = A[row][ai[j]];
+  };
+  const int qv = h ? B_QR : B_QL, qd = h ? B_DRT1 : B_DLT1, qn = h ? B_DRN : B_DLN;
+  const int av = h ? 5 : 0, an = h ? 15 : 10;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    R v[5], val, der;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[0 + k][ai[j]];
-    gauss_value_slope(v, gp, val, der);
-    out[(B_QL + k) * qstride] = val;
-    out[(B_DLT1 + k) * qstride] = der;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[5 + k][ai[j]];
-    gauss_value_slope(v, gp, val, der);
-    out[(B_QR + k) * qstride] = val;
-    out[(B_DRT1 + k) * qstride] = der;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[10 + k][ai[j]];
-    out[(B_DLN + k) * qstride] = gauss_value(v, gp);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[15 + k][ai[j]];
-    out[(B_DRN + k) * qstride] = gauss_value(v, gp);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[20 + k][ai[j]];
-    out[(B_D0 + k) * qstride] = gauss_linear(v, gp);
+    R v[5], val[2], der[2];
+    stencil(av + k, v);
+    gauss_value_slope2(v, val, der);
+    put(qv + k, val);
+    put(qd + k, der);
+    stencil(an + k, v);
+    gauss_value2(v, val);
+    put(qn + k, val);
+  }
+  const int k0 = h ? 3 : 0, k1 = h ? 5 : 3;
+  for (int k = k0; k < k1; ++k) {
+    R v[5], val[2];
+    stencil(20 + k, v);
+    gauss_linear2(v, val);
+    put(B_D0 + k, val);
   }
 }
 

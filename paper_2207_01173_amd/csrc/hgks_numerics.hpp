@@ -50,29 +50,44 @@ __device__ __forceinline__ Candidates<R> candidates(const R v[5]) {
 }
 
 // Nonlinear weights alpha_k = d_k (1 + tau5 / b_k), b_k = beta_k + eps,
-// normalised.  Multiplying every alpha by b0 b1 b2 leaves the normalised
-// weights unchanged and needs a single reciprocal (FP64: the products stay far
-// from underflow for b >= eps).  The FP32 path keeps one reciprocal per b_k,
-// whose products could underflow.
+// normalised.  wz_factors gives e_k with alpha_k proportional to d_k e_k; they
+// depend on the stencil only, so every set of linear weights (both Gauss
+// points, value and slope weights) shares them.  Multiplying every alpha by
+// b0 b1 b2 leaves the normalised weights unchanged and needs a single
+// reciprocal per set (FP64: the products stay far from underflow for b >=
+// eps).  The FP32 path keeps one reciprocal per b_k, whose products could
+// underflow.
 template <class R>
-__device__ __forceinline__ void wz_weights(const R beta[3], R d0, R d1, R d2, R w[3]) {
+__device__ __forceinline__ void wz_factors(const R beta[3], R e[3]) {
   const R eps = WenoEps<R>::v;
   const R t5 = fabs(beta[0] - beta[2]);
   const R b0 = beta[0] + eps, b1 = beta[1] + eps, b2 = beta[2] + eps;
-  R a0, a1, a2;
   if (sizeof(R) == 8) {
-    a0 = d0 * (b0 + t5) * (b1 * b2);
-    a1 = d1 * (b1 + t5) * (b0 * b2);
-    a2 = d2 * (b2 + t5) * (b0 * b1);
+    e[0] = (b0 + t5) * (b1 * b2);
+    e[1] = (b1 + t5) * (b0 * b2);
+    e[2] = (b2 + t5) * (b0 * b1);
   } else {
-    a0 = d0 * (R(1) + t5 * pos_rcp(b0));
-    a1 = d1 * (R(1) + t5 * pos_rcp(b1));
-    a2 = d2 * (R(1) + t5 * pos_rcp(b2));
+    e[0] = R(1) + t5 * pos_rcp(b0);
+    e[1] = R(1) + t5 * pos_rcp(b1);
+    e[2] = R(1) + t5 * pos_rcp(b2);
   }
+}
+
+// Normalised weights alpha_k / sum alpha for the linear weights (d0, d1, d2).
+template <class R>
+__device__ __forceinline__ void wz_normalise(const R e[3], R d0, R d1, R d2, R w[3]) {
+  const R a0 = d0 * e[0], a1 = d1 * e[1], a2 = d2 * e[2];
   const R inv = pos_rcp(a0 + a1 + a2);
   w[0] = a0 * inv;
   w[1] = a1 * inv;
   w[2] = a2 * inv;
+}
+
+template <class R>
+__device__ __forceinline__ void wz_weights(const R beta[3], R d0, R d1, R d2, R w[3]) {
+  R e[3];
+  wz_factors(beta, e);
+  wz_normalise(e, d0, d1, d2, w);
 }
 
 // Gauss points of the unit cell: s = -sqrt(3)/6 (g = 0) and +sqrt(3)/6 (g = 1).
@@ -122,6 +137,51 @@ __device__ __forceinline__ void gauss_value_slope(const R v[5], const GaussPoint
   val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
   wz_weights(k.beta, gp.dd0, gp.dd1, gp.dd2, w);
   der = w[0] * (k.b[0] + k.c[0] * gp.s) + w[1] * (k.b[1] + k.c[1] * gp.s) + w[2] * (k.b[2] + k.c[2] * gp.s);
+}
+
+// Both Gauss points of one stencil (index 0: s = -sqrt3/6, 1: s = +sqrt3/6)
+// from one set of candidates and WENO-Z factors; the same arithmetic as
+// gauss_value / gauss_value_slope at each point.
+template <class R>
+__device__ __forceinline__ void gauss_value2(const R v[5], R val[2]) {
+  const Candidates<R> k = candidates(v);
+  R e[3], w[3];
+  wz_factors(k.beta, e);
+  const R s = R(GaussConst::s);
+  const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
+  wz_normalise(e, d2, d1, d0, w);
+  val[0] = v[2] - s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, d0, d1, d2, w);
+  val[1] = v[2] + s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+}
+
+template <class R>
+__device__ __forceinline__ void gauss_value_slope2(const R v[5], R val[2], R der[2]) {
+  const Candidates<R> k = candidates(v);
+  R e[3], w[3];
+  wz_factors(k.beta, e);
+  const R s = R(GaussConst::s);
+  const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
+  const R g0 = R(GaussConst::dd0), g1 = R(GaussConst::dd1), g2 = R(GaussConst::dd2);
+  wz_normalise(e, d2, d1, d0, w);
+  val[0] = v[2] - s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, g2, g1, g0, w);
+  der[0] = w[0] * (k.b[0] - k.c[0] * s) + w[1] * (k.b[1] - k.c[1] * s) + w[2] * (k.b[2] - k.c[2] * s);
+  wz_normalise(e, d0, d1, d2, w);
+  val[1] = v[2] + s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, g0, g1, g2, w);
+  der[1] = w[0] * (k.b[0] + k.c[0] * s) + w[1] * (k.b[1] + k.c[1] * s) + w[2] * (k.b[2] + k.c[2] * s);
+}
+
+template <class R>
+__device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
+  const R b0 = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
+  const R b1 = R(0.5) * (v[3] - v[1]);
+  const R b2 = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
+  const R s = R(GaussConst::s);
+  const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
+  val[0] = v[2] - s * (d2 * b0 + d1 * b1 + d0 * b2);
+  val[1] = v[2] + s * (d0 * b0 + d1 * b1 + d2 * b2);
 }
 
 // Linear (fifth-order) value at a Gauss point: the quartic through the averages.
