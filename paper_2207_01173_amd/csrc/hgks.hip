@@ -71,6 +71,12 @@ __host__ __device__ inline void face_extents(const Params& P, int d, int fe[3]) 
   for (int a = 0; a < 3; ++a) fe[a] = P.n[a] + (a == d ? 1 : 0);
 }
 
+// Row pitch of the face arrays (buffer B and the face fluxes F): the x extent
+// rounded up to 32 elements, so that every row starts on a 128-byte boundary
+// and a tile's 16-face rows do not straddle cache lines (direction x has n + 1
+// faces along x).
+__host__ __device__ inline int face_pitch(int nx) { return (nx + 31) & ~31; }
+
 // Tile order across the grid of blocks: tile index `fast` varies fastest
 // (neighbouring tiles along that axis share stencil data), and the blocks are
 // remapped so that each of the 8 XCDs (which take blocks round robin and have
@@ -256,8 +262,9 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
     l[D1] += j;  // A tile is offset by -2 along t1
     ai[j] = (l[2] * SA[1] + l[1]) * SA[0] + l[0];
   }
-  const size_t NB = (size_t)be[0] * be[1] * be[2];
-  const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * be[0] + (f[0] - bo[0]);
+  const int bp = face_pitch(be[0]);
+  const size_t NB = (size_t)bp * be[1] * be[2];
+  const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * bp + (f[0] - bo[0]);
   HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
   const size_t qstride = 2 * NB;
   auto put = [&](int q, const R val[2]) {
@@ -344,7 +351,8 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
 
   // ---- second tangential sweep along t2 ----------------------------------
-  const size_t NB = (size_t)be[0] * be[1] * be[2];
+  const int bp = face_pitch(be[0]);
+  const size_t NB = (size_t)bp * be[1] * be[2];
   const size_t qstride = 2 * NB;
   // Lane byte offsets within one quantity's two Gauss lines (below 2^32:
   // checked when the configuration is validated), added to a per-quantity base
@@ -357,7 +365,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
     bi[j] = (uint32_t)(sizeof(R) *
-                       ((size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * be[0] + (b[0] - bo[0])));
+                       ((size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * bp + (b[0] - bo[0])));
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
@@ -498,8 +506,9 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     loc[k] = (4.0 * I2 - I1) * idt;
     loc[5 + k] = (I1 - 2.0 * I2) * idt2;
   }
-  const size_t NF = (size_t)fe[0] * fe[1] * fe[2];
-  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fe[0] + f[0];
+  const int fpitch = face_pitch(fe[0]);
+  const size_t NF = (size_t)fpitch * fe[1] * fe[2];
+  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fpitch + f[0];
   // rotate momentum back to the global frame
   const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
   HGKS_GLOBAL double* Fg = gmem(F);
@@ -534,9 +543,10 @@ __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, con
   for (int d = 0; d < 3; ++d) {
     int fe[3];
     face_extents(P, d, fe);
-    const size_t NF = (size_t)fe[0] * fe[1] * fe[2];
-    const size_t fm = ((size_t)k * fe[1] + j) * fe[0] + i;
-    const size_t step = d == 0 ? 1 : (d == 1 ? (size_t)fe[0] : (size_t)fe[0] * fe[1]);
+    const int fpitch = face_pitch(fe[0]);
+    const size_t NF = (size_t)fpitch * fe[1] * fe[2];
+    const size_t fm = ((size_t)k * fe[1] + j) * fpitch + i;
+    const size_t step = d == 0 ? 1 : (d == 1 ? (size_t)fpitch : (size_t)fpitch * fe[1]);
     const size_t fp = fm + step;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
@@ -910,14 +920,14 @@ Layout make_layout(const hgks_config& c) {
   for (int d = 0; d < 3; ++d) {
     int be[3], bo[3];
     b_extents(P, d, be, bo);
-    nb = std::max(nb, (size_t)be[0] * be[1] * be[2]);
+    nb = std::max(nb, (size_t)face_pitch(be[0]) * be[1] * be[2]);
   }
   L.nb_elems = (size_t)B_COUNT * 2 * nb;
   L.B = take(L.nb_elems * (precision_mixed(c) ? sizeof(float) : sizeof(double)));
   for (int d = 0; d < 3; ++d) {
     int fe[3];
     face_extents(P, d, fe);
-    L.F[d] = take((size_t)10 * fe[0] * fe[1] * fe[2] * sizeof(double));
+    L.F[d] = take((size_t)10 * face_pitch(fe[0]) * fe[1] * fe[2] * sizeof(double));
   }
   for (int a = 0; a < 3; ++a) {
     L.metric[a][0] = take(c.n[a] * sizeof(double));            // hcell
@@ -1036,7 +1046,7 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
     for (int d = 0; d < 3; ++d) {
       int be[3], bo[3];
       b_extents(P, d, be, bo);
-      if (2 * sizeof(double) * be[0] * be[1] * be[2] >= ((size_t)1 << 32)) return bad("grid too large");
+      if (2 * sizeof(double) * face_pitch(be[0]) * be[1] * be[2] >= ((size_t)1 << 32)) return bad("grid too large");
     }
   }
   if (!(c->gamma > 1.0 && c->gamma <= 5.0 / 3.0)) return bad("gamma out of (1, 5/3]");
