@@ -388,40 +388,49 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.iT_ref = R(P.T_ref > 0.0 ? 1.0 / P.T_ref : 0.0);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
-  // Five stencil values of quantity qi along t2.
+  // Five stencil values of quantity qi along t2 (qi the same on every lane).
   auto stencil = [&](int qi, R v[5]) {
     const HGKS_GLOBAL char* base = reinterpret_cast<const HGKS_GLOBAL char*>(Bg + (size_t)qi * qstride);
 #pragma unroll
     for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(base + bi[j]);
   };
+  // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
+  // lane ^ 16) share every t2 stencil.  Each reconstructs one of two
+  // quantities at both points (its own and the mirrored one) and swaps the
+  // mirrored result with its partner.  The g2 = 0 lane takes Q^l, the normal
+  // slopes; the g2 = 1 lane Q^r, the t1 slopes.
+  const bool second = g2 != 0;
+  auto stencil_pair = [&](int qi0, int dqi, R v[5]) {
+    const HGKS_GLOBAL char* base =
+        reinterpret_cast<const HGKS_GLOBAL char*>(Bg + ((size_t)qi0 + (second ? dqi : 0)) * qstride);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(base + bi[j]);
+  };
+  auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
 
   // Raw t2 stencils of a phase's inputs.  On the FP64 path (one wave per SIMD,
   // so nothing else hides memory latency) each phase issues the loads of the
   // next phase before its own arithmetic; on the FP32 path the registers that
   // takes would cost a wave of occupancy, so each phase loads its own.
   constexpr bool kPrefetch = sizeof(R) == 8;
-  R pa[5][5], pb[5][5];
+  R pa[5][5];
 
   // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
   R ql[5], qr[5], tl2[5], tr2[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    R v[5], val, der;
-    stencil(B_QL + k, v);
-    gauss_value_slope(v, gp, val, der);
-    ql[k] = R(double(val) + rl[k]);
-    tl2[k] = der * st2;
-    stencil(B_QR + k, v);
-    gauss_value_slope(v, gp, val, der);
-    qr[k] = R(double(val) + rl[k]);
-    tr2[k] = der * st2;
+    R v[5], val, der, val_m, der_m;
+    stencil_pair(B_QL + k, B_QR - B_QL, v);
+    gauss_value_slope_mirror(v, gp, val, der, val_m, der_m);
+    const R ov = partner(val_m), od = partner(der_m);  // the other state at this lane's point
+    ql[k] = R(double(second ? ov : val) + rl[k]);
+    tl2[k] = (second ? od : der) * st2;
+    qr[k] = R(double(second ? val : ov) + rl[k]);
+    tr2[k] = (second ? der : od) * st2;
   }
   if (kPrefetch) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      stencil(B_DLN + k, pa[k]);
-      stencil(B_DLT1 + k, pb[k]);
-    }
+    for (int k = 0; k < 5; ++k) stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
@@ -432,20 +441,17 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (!kPrefetch) {
-        stencil(B_DLN + k, pa[k]);
-        stencil(B_DLT1 + k, pb[k]);
-      }
-      dq[0][k] = gauss_value(pa[k], gp) * sn;
-      dq[1][k] = gauss_value(pb[k], gp) * st1;
+      if (!kPrefetch) stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
+      R val, val_m;
+      gauss_value_mirror(pa[k], gp, val, val_m);
+      const R o = partner(val_m);
+      dq[0][k] = (second ? o : val) * sn;
+      dq[1][k] = (second ? val : o) * st1;
       dq[2][k] = tl2[k];
     }
     if (kPrefetch) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        stencil(B_DRN + k, pa[k]);
-        stencil(B_DRT1 + k, pb[k]);
-      }
+      for (int k = 0; k < 5; ++k) stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
     }
     flux_side<R, true>(ql, dq, g, acc);
   }
@@ -456,12 +462,12 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (!kPrefetch) {
-        stencil(B_DRN + k, pa[k]);
-        stencil(B_DRT1 + k, pb[k]);
-      }
-      dq[0][k] = gauss_value(pa[k], gp) * sn;
-      dq[1][k] = gauss_value(pb[k], gp) * st1;
+      if (!kPrefetch) stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
+      R val, val_m;
+      gauss_value_mirror(pa[k], gp, val, val_m);
+      const R o = partner(val_m);
+      dq[0][k] = (second ? o : val) * sn;
+      dq[1][k] = (second ? val : o) * st1;
       dq[2][k] = tr2[k];
     }
     if (kPrefetch) {

@@ -184,6 +184,36 @@ __device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
   val[1] = v[2] + s * (d0 * b0 + d1 * b1 + d2 * b2);
 }
 
+// WENO-Z at a lane's Gauss point (gp) and at the mirrored point -s (whose
+// linear weights are gp's reversed), from one set of candidates and factors.
+// At each point the arithmetic is that of gauss_value / gauss_value_slope.
+template <class R>
+__device__ __forceinline__ void gauss_value_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& val_m) {
+  const Candidates<R> k = candidates(v);
+  R e[3], w[3];
+  wz_factors(k.beta, e);
+  wz_normalise(e, gp.dv0, gp.dv1, gp.dv2, w);
+  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, gp.dv2, gp.dv1, gp.dv0, w);
+  val_m = v[2] - gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+}
+
+template <class R>
+__device__ __forceinline__ void gauss_value_slope_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& der,
+                                                         R& val_m, R& der_m) {
+  const Candidates<R> k = candidates(v);
+  R e[3], w[3];
+  wz_factors(k.beta, e);
+  wz_normalise(e, gp.dv0, gp.dv1, gp.dv2, w);
+  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, gp.dd0, gp.dd1, gp.dd2, w);
+  der = w[0] * (k.b[0] + k.c[0] * gp.s) + w[1] * (k.b[1] + k.c[1] * gp.s) + w[2] * (k.b[2] + k.c[2] * gp.s);
+  wz_normalise(e, gp.dv2, gp.dv1, gp.dv0, w);
+  val_m = v[2] - gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  wz_normalise(e, gp.dd2, gp.dd1, gp.dd0, w);
+  der_m = w[0] * (k.b[0] - k.c[0] * gp.s) + w[1] * (k.b[1] - k.c[1] * gp.s) + w[2] * (k.b[2] - k.c[2] * gp.s);
+}
+
 // Linear (fifth-order) value at a Gauss point: the quartic through the averages.
 template <class R>
 __device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp) {
