@@ -306,6 +306,10 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __re
 }
 
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
+// At least two blocks (two waves per SIMD) resident per CU: the FP64 kernel is
+// held to 256 registers per lane, spilling a few phase-1 values that only
+// phase 4 reads, so that a second wave hides each phase's load latency.
+constexpr int FLUX_MIN_BLOCKS = 2;
 
 // Flux tiles: 64 faces, TX along x times 64/TX along y, one z plane.
 template <int TX> __host__ __device__ inline void flux_tile_counts(const Params& P, int d, int nt[3]) {
@@ -408,11 +412,8 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   };
   auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
 
-  // Raw t2 stencils of a phase's inputs.  On the FP64 path (one wave per SIMD,
-  // so nothing else hides memory latency) each phase issues the loads of the
-  // next phase before its own arithmetic; on the FP32 path the registers that
-  // takes would cost a wave of occupancy, so each phase loads its own.
-  constexpr bool kPrefetch = sizeof(R) == 8;
+  // Each phase loads its own raw t2 stencils; the kernels run at least two
+  // waves per SIMD (launch bounds), so the other wave covers their latency.
   R pa[5][5];
 
   // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
@@ -428,10 +429,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     qr[k] = R(double(second ? val : ov) + rl[k]);
     tr2[k] = (second ? der : od) * st2;
   }
-  if (kPrefetch) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
-  }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
   __builtin_amdgcn_sched_barrier(0);
@@ -441,17 +438,13 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (!kPrefetch) stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
+      stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
       R val, val_m;
       gauss_value_mirror(pa[k], gp, val, val_m);
       const R o = partner(val_m);
       dq[0][k] = (second ? o : val) * sn;
       dq[1][k] = (second ? val : o) * st1;
       dq[2][k] = tl2[k];
-    }
-    if (kPrefetch) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
     }
     flux_side<R, true>(ql, dq, g, acc);
   }
@@ -462,17 +455,13 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (!kPrefetch) stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
+      stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
       R val, val_m;
       gauss_value_mirror(pa[k], gp, val, val_m);
       const R o = partner(val_m);
       dq[0][k] = (second ? o : val) * sn;
       dq[1][k] = (second ? val : o) * st1;
       dq[2][k] = tr2[k];
-    }
-    if (kPrefetch) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) stencil(B_D0 + k, pa[k]);
     }
     flux_side<R, false>(qr, dq, g, acc);
   }
@@ -484,7 +473,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq0n[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (!kPrefetch) stencil(B_D0 + k, pa[k]);
+      stencil(B_D0 + k, pa[k]);
       dq0n[k] = gauss_linear(pa[k], gp) * sn;
     }
     flux_finish(dq0n, g, acc, F1, F2);
@@ -526,7 +515,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
 }
 
 template <int DIR, class R>
-__global__ __launch_bounds__(FLUX_THREADS) void flux_kernel(const R* __restrict__ B, Params P,
+__global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_kernel(const R* __restrict__ B, Params P,
                                                             const double* __restrict__ qref,
                                                             const Scalars* __restrict__ sc, int use_residual_dt,
                                                             double* __restrict__ F) {
@@ -858,7 +847,7 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T
 }
 
 template <int DIR, class R, int TX>
-__global__ __launch_bounds__(FLUX_THREADS) void flux_batch_kernel(BatchTable T, int t0, int t1) {
+__global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_batch_kernel(BatchTable T, int t0, int t1) {
   const int t = t0 + xcd_linear_block(gridDim.x);
   if (t >= t1) return;
   int local;
