@@ -431,7 +431,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
-  __builtin_amdgcn_sched_barrier(0);
 
   // phase 2: left side
   {
@@ -448,7 +447,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     }
     flux_side<R, true>(ql, dq, g, acc);
   }
-  __builtin_amdgcn_sched_barrier(0);
 
   // phase 3: right side
   {
@@ -465,7 +463,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     }
     flux_side<R, false>(qr, dq, g, acc);
   }
-  __builtin_amdgcn_sched_barrier(0);
 
   // phase 4: equilibrium part and Prandtl correction
   R F1[5], F2[5];
