@@ -45,9 +45,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "65898866345d021b6b74c7a00b2e88e23d862f08e3517c3d08b5e8ce61b488f0",
-    "fetch_bytes": 9.6838e+09,
-    "write_bytes": 1.3527e+09,
+    "sources_sha256": "e8198c15ec35b422508ea12bca7cdb96414ee57ec780ad28bd55e59497861ea2",
+    "fetch_bytes": 1.0191e+10,
+    "write_bytes": 3.0509e+09,
 }
 
 # MI355X published peaks
