@@ -267,9 +267,11 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * bp + (f[0] - bo[0]);
   HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
   const size_t qstride = 2 * NB;
+  // B is written once and read once, by the flux kernel: non-temporal stores
+  // (no L2 allocation for a stream many times the cache's size).
   auto put = [&](int q, const R val[2]) {
-    out[q * qstride] = val[0];
-    out[q * qstride + NB] = val[1];
+    __builtin_nontemporal_store(val[0], &out[q * qstride]);
+    __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
   };
   auto stencil = [&](int row, R v[5]) {
 #pragma unroll
