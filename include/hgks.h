@@ -45,7 +45,16 @@
 extern "C" {
 #endif
 
-#define HGKS_ABI_VERSION 1
+#define HGKS_ABI_VERSION 2
+
+/* hgks_config.flags bit 0: constant streamwise mass flux (Sec. 4.2, where a
+ * constant streamwise momentum flux determines the external force).  The
+ * target is the volume mean of rho U of the state given to hgks_init; after
+ * each step the x body force becomes f - (2 e^{n+1} - e^n) / (rho_b dt), e the
+ * deviation of the step's mean rho U from the target, rho_b the initial mean
+ * density; body_force[0] is the starting force.  Single-instance contexts
+ * only (hgks_batch_* return HGKS_E_UNSUPPORTED). */
+#define HGKS_FLAG_CONSTANT_MASS_FLUX 1
 
 typedef struct hgks_ctx_s* hgks_ctx;
 
@@ -76,7 +85,7 @@ typedef struct {
   double cfl;            /* CFL number of the time-step rule when dt is not fixed */
   double rho_ref;        /* rho0 of the statistics normalisation (> 0) */
   int32_t precision;     /* HGKS_FP64 or HGKS_MIXED */
-  int32_t flags;         /* reserved, must be 0 */
+  int32_t flags;         /* 0 or HGKS_FLAG_CONSTANT_MASS_FLUX */
 } hgks_config;
 
 typedef struct {
@@ -92,6 +101,7 @@ typedef struct {
   double min_p, min_rho; /* minima of pressure and density */
   int32_t nonfinite;     /* 1 if any NaN/Inf was found */
   int32_t pad_;
+  double body_force_x;   /* x body force in effect (the controller's with the mass-flux flag) */
 } hgks_stats_t;
 
 /* Workspace bytes for a configuration.  Errors: HGKS_E_INVALID. */

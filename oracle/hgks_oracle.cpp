@@ -770,6 +770,7 @@ struct Config {
   double T_wall;
   double body_force[3];
   double cfl;
+  int32_t flags;       // bit 0: constant streamwise mass flux (force from a controller, R24)
 };
 
 static const int G = 3;  // ghost layers
@@ -1380,16 +1381,51 @@ double hgo_cfl_dt(const hgo_config* cfg, const double* q) {
   build_grid(*cfg, g);
   return cfl_dt(g, q);
 }
-/* Advance nsteps; dt_fixed <= 0 uses the CFL rule each step. Returns the last dt. */
-double hgo_step(const hgo_config* cfg, double* q, int nsteps, double dt_fixed) {
+/* Advance nsteps; dt_fixed <= 0 uses the CFL rule each step. Returns the last
+ * dt.  With flags bit 0 the streamwise force follows the constant-mass-flux
+ * controller (Sec. 4.2 fixes the force by a constant streamwise momentum flux;
+ * the rule is reading R24): target m_t = volume mean of rho U of the initial
+ * state, rho_b its mean density, and after each step with error e = m - m_t,
+ * f <- f - (2 e^{n+1} - e^n) / (rho_b dt), the step that brings the error to
+ * zero over the next step if the wall drag stays what the last step showed.
+ * The force in effect after the last step is returned in *force_out.        */
+double hgo_step_force(const hgo_config* cfg, double* q, int nsteps, double dt_fixed, double* force_out) {
   Grid g;
   build_grid(*cfg, g);
+  const bool control = (cfg->flags & 1) != 0;
+  // volume means of rho and rho U
+  auto means = [&](double& rho_m, double& m_m) {
+    double vs = 0.0, rs = 0.0, ms = 0.0;
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          double v = g.h[0][i] * g.h[1][j] * g.h[2][k];
+          vs += v;
+          rs += v * q[sidx(g, 0, i, j, k)];
+          ms += v * q[sidx(g, 1, i, j, k)];
+        }
+    rho_m = rs / vs;
+    m_m = ms / vs;
+  };
+  double rho_b = 0.0, m_t = 0.0;
+  if (control) means(rho_b, m_t);
+  double m_prev = m_t;
   double dt = dt_fixed;
   for (int s = 0; s < nsteps; ++s) {
     dt = dt_fixed > 0.0 ? dt_fixed : cfl_dt(g, q);
     s2o4_step(g, q, dt);
+    if (control) {
+      double r, m;
+      means(r, m);
+      g.c.body_force[0] -= (2.0 * (m - m_t) - (m_prev - m_t)) / (rho_b * dt);
+      m_prev = m;
+    }
   }
+  if (force_out) *force_out = g.c.body_force[0];
   return dt;
+}
+double hgo_step(const hgo_config* cfg, double* q, int nsteps, double dt_fixed) {
+  return hgo_step_force(cfg, q, nsteps, dt_fixed, nullptr);
 }
 /* One S2O4 stage pair on a scalar linear ODE q' = lam q with exact L and dL/dt
  * (for the amplification-polynomial pin): returns q^{n+1}.                   */

@@ -44,6 +44,7 @@ class Config(ctypes.Structure):
         ("T_wall", ctypes.c_double),
         ("body_force", ctypes.c_double * 3),
         ("cfl", ctypes.c_double),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -63,6 +64,7 @@ def make_config(p: dict) -> Config:
     c.mu_exp = float(p.get("mu_exp", 0.0))
     c.T_wall = float(p.get("T_wall", 1.0))
     c.cfl = float(p.get("cfl", 0.5))
+    c.flags = 1 if p.get("mass_flux_control") else 0
     return c
 
 
@@ -108,6 +110,8 @@ def lib():
         L.hgo_cfl_dt.restype = d
         L.hgo_step.argtypes = [P, _D, i, d]
         L.hgo_step.restype = d
+        L.hgo_step_force.argtypes = [P, _D, i, d, _D]
+        L.hgo_step_force.restype = d
         L.hgo_s2o4_scalar.argtypes = [d, d, d]
         L.hgo_s2o4_scalar.restype = d
         L.hgo_stats.argtypes = [P, _D, d, _D]
@@ -287,10 +291,19 @@ def cfl_dt(p: dict, q: np.ndarray) -> float:
 
 def step(p: dict, q: np.ndarray, nsteps: int, dt_fixed: float = 0.0):
     """Advance a copy of q by nsteps S2O4 steps; returns (q_new, last_dt)."""
+    q, dt, _ = step_force(p, q, nsteps, dt_fixed)
+    return q, dt
+
+
+def step_force(p: dict, q: np.ndarray, nsteps: int, dt_fixed: float = 0.0):
+    """As step, also returning the streamwise force in effect after the last
+    step (changed by the constant-mass-flux controller when
+    p["mass_flux_control"] is set)."""
     cfg = make_config(p)
     q = _q(np.array(q, dtype=np.float64, order="C", copy=True), cfg)
-    dt = lib().hgo_step(ctypes.byref(cfg), _ptr(q), int(nsteps), float(dt_fixed))
-    return q, float(dt)
+    f = ctypes.c_double(0.0)
+    dt = lib().hgo_step_force(ctypes.byref(cfg), _ptr(q), int(nsteps), float(dt_fixed), ctypes.byref(f))
+    return q, float(dt), float(f.value)
 
 
 def s2o4_scalar(q, lam, dt):

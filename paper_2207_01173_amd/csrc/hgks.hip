@@ -35,6 +35,7 @@ enum {
 struct Params {
   int n[3];
   int bc[3];
+  int flags;  // hgks_config.flags
   double gamma, gm1, K, mu_ref, T_ref, mu_exp, pr_fix, T_wall;
   double force[3];
   const double* hcell[3];  // cell widths
@@ -50,7 +51,9 @@ struct Scalars {
   double dt_residual;        // time step used by hgks_residual
   double steps;              // steps taken
   unsigned long long smax;   // bit pattern of max wave speed / h (positive double)
-  unsigned long long pad[3];
+  double force_x;            // streamwise body force in effect (the controller's, with the mass-flux flag)
+  double m_prev;             // volume mean of rho U after the last step (mass-flux controller)
+  double pad;
 };
 
 // Global-memory view of a device pointer.  A pointer that a kernel reads out
@@ -526,7 +529,8 @@ __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_kernel(con
 // S = (0, rho f, m . f) and its time derivative (0, f L_rho, f . L_m).
 __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, const double* __restrict__ F0,
                                               const double* __restrict__ F1, const double* __restrict__ F2,
-                                              const Params& P, int i, int j, int k, double L[5], double dL[5]) {
+                                              const Params& P, const double fb[3], int i, int j, int k, double L[5],
+                                              double dL[5]) {
   const size_t n3 = cells(P);
   const size_t c = ((size_t)k * P.n[1] + j) * P.n[0] + i;
   const double vol = gmem(P.hcell[0])[i] * gmem(P.hcell[1])[j] * gmem(P.hcell[2])[k];
@@ -551,14 +555,14 @@ __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, con
   const HGKS_GLOBAL double* qg = gmem(qe);
   const double rho = qg[c], mx = qg[n3 + c], my = qg[2 * n3 + c], mz = qg[3 * n3 + c];
   const double lrho = L[0];
-  L[1] += rho * P.force[0];
-  L[2] += rho * P.force[1];
-  L[3] += rho * P.force[2];
-  L[4] += mx * P.force[0] + my * P.force[1] + mz * P.force[2];
-  dL[1] += P.force[0] * lrho;
-  dL[2] += P.force[1] * lrho;
-  dL[3] += P.force[2] * lrho;
-  dL[4] += P.force[0] * L[1] + P.force[1] * L[2] + P.force[2] * L[3];
+  L[1] += rho * fb[0];
+  L[2] += rho * fb[1];
+  L[3] += rho * fb[2];
+  L[4] += mx * fb[0] + my * fb[1] + mz * fb[2];
+  dL[1] += fb[0] * lrho;
+  dL[2] += fb[1] * lrho;
+  dL[3] += fb[2] * lrho;
+  dL[4] += fb[0] * L[1] + fb[1] * L[2] + fb[2] * L[3];
 }
 
 // Wave speed max_d (|U_d| + c) / h_d of one cell.
@@ -589,6 +593,22 @@ __device__ __forceinline__ void block_max_atomic(double r, unsigned long long* d
   __syncthreads();  // red[] may be reused by the next call in this block
 }
 
+// Block sum in a fixed order (wave shuffles, then the waves in order), stored
+// by thread 0: deterministic.
+__device__ __forceinline__ void block_sum_store(double x, double* dst) {
+  __shared__ double red[16];
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    *dst = t;
+  }
+  __syncthreads();  // red[] may be reused by the next call in this block
+}
+
 constexpr int CELL_THREADS = 256;
 
 // S2O4 stage for cell block `blk` (CELL_THREADS cells) of one instance.
@@ -596,13 +616,14 @@ template <int STAGE>
 __device__ __forceinline__ void update_block(double* __restrict__ q, double* __restrict__ qs, double* __restrict__ acc,
                                              const double* __restrict__ F0, const double* __restrict__ F1,
                                              const double* __restrict__ F2, const Params& P, Scalars* __restrict__ sc,
-                                             size_t blk) {
+                                             double* __restrict__ mpart, size_t blk) {
   const size_t n3 = cells(P);
   const size_t c = blk * CELL_THREADS + threadIdx.x;
   HGKS_GLOBAL double* qg = gmem(q);
   HGKS_GLOBAL double* qsg = gmem(qs);
   HGKS_GLOBAL double* accg = gmem(acc);
-  double rate = 0.0;
+  const double fb[3] = {gmem(sc)->force_x, P.force[1], P.force[2]};
+  double rate = 0.0, mflux = 0.0;
   if (c < n3) {
     const int i = (int)(c % P.n[0]);
     const int j = (int)((c / P.n[0]) % P.n[1]);
@@ -610,7 +631,7 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
     const double dt = gmem(sc)->dt;
     double L[5], dL[5];
     if (STAGE == 1) {
-      cell_residual(q, F0, F1, F2, P, i, j, k, L, dL);
+      cell_residual(q, F0, F1, F2, P, fb, i, j, k, L, dL);
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const double qn = qg[m * n3 + c];
@@ -618,7 +639,7 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
         accg[m * n3 + c] = qn + dt * L[m] + dt * dt / 6.0 * dL[m];
       }
     } else {
-      cell_residual(qs, F0, F1, F2, P, i, j, k, L, dL);
+      cell_residual(qs, F0, F1, F2, P, fb, i, j, k, L, dL);
       double v[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
@@ -626,9 +647,14 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
         qg[m * n3 + c] = v[m];
       }
       rate = cell_wave_rate(v, P, i, j, k);
+      if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX)
+        mflux = v[1] * gmem(P.hcell[0])[i] * gmem(P.hcell[1])[j] * gmem(P.hcell[2])[k];
     }
   }
-  if (STAGE == 2) block_max_atomic(rate, &sc->smax);
+  if (STAGE == 2) {
+    block_max_atomic(rate, &sc->smax);
+    if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX) block_sum_store(mflux, &mpart[blk]);
+  }
 }
 
 template <int STAGE>
@@ -636,14 +662,15 @@ __global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict
                                                               double* __restrict__ acc, const double* __restrict__ F0,
                                                               const double* __restrict__ F1,
                                                               const double* __restrict__ F2, Params P,
-                                                              Scalars* __restrict__ sc) {
-  update_block<STAGE>(q, qs, acc, F0, F1, F2, P, sc, blockIdx.x);
+                                                              Scalars* __restrict__ sc, double* __restrict__ mpart) {
+  update_block<STAGE>(q, qs, acc, F0, F1, F2, P, sc, mpart, blockIdx.x);
 }
 
 __global__ __launch_bounds__(CELL_THREADS) void residual_kernel(const double* __restrict__ qe,
                                                                 const double* __restrict__ F0,
                                                                 const double* __restrict__ F1,
                                                                 const double* __restrict__ F2, Params P,
+                                                                const Scalars* __restrict__ sc,
                                                                 double* __restrict__ Lo, double* __restrict__ dLo) {
   const size_t n3 = cells(P);
   const size_t c = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
@@ -652,7 +679,8 @@ __global__ __launch_bounds__(CELL_THREADS) void residual_kernel(const double* __
   const int j = (int)((c / P.n[0]) % P.n[1]);
   const int k = (int)(c / ((size_t)P.n[0] * P.n[1]));
   double L[5], dL[5];
-  cell_residual(qe, F0, F1, F2, P, i, j, k, L, dL);
+  const double fb[3] = {sc->force_x, P.force[1], P.force[2]};
+  cell_residual(qe, F0, F1, F2, P, fb, i, j, k, L, dL);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     Lo[m * n3 + c] = L[m];
@@ -860,7 +888,7 @@ __global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T
   if (t >= t1) return;
   int local;
   const BatchEntry& e = T.E[find_instance(T, PRE_CELL, t, local)];
-  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, (size_t)local);
+  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, nullptr, (size_t)local);
 }
 
 // Start of a batched step: each instance takes its own CFL time step.
@@ -882,6 +910,40 @@ __global__ void mean_state_kernel(const double* __restrict__ fin, double inv_vol
   if (threadIdx.x < 5) qref[threadIdx.x] = fin[ST_TOT + threadIdx.x] * inv_vol;
 }
 
+// Constant streamwise mass flux (Sec. 4.2: the external force follows from a
+// constant streamwise momentum flux).  At init: the target m_t and the mean
+// density rho_b are the volume means of rho U and rho of the initial state.
+// After each step, with e = m - m_t for the step's volume mean m of rho U,
+// f <- f - (2 e^{n+1} - e^n) / (rho_b dt): the force that brings the error to
+// zero over the next step if the wall drag stays what the last step showed.
+// mf = {rho_b, m_t}.
+__global__ void mass_flux_init_kernel(const double* __restrict__ fin, double inv_vol, double* __restrict__ mf,
+                                      Scalars* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  mf[0] = fin[ST_TOT + 0] * inv_vol;
+  mf[1] = fin[ST_TOT + 1] * inv_vol;
+  sc->m_prev = mf[1];
+}
+
+__global__ __launch_bounds__(256) void mass_flux_kernel(const double* __restrict__ mpart, int nb, double inv_vol,
+                                                        const double* __restrict__ mf, Scalars* __restrict__ sc) {
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) t += mpart[b];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = red[0] * inv_vol, mt = mf[1];
+    const double e1 = m - mt, e0 = sc->m_prev - mt;
+    sc->force_x -= (2.0 * e1 - e0) / (mf[0] * sc->dt);
+    sc->m_prev = m;
+  }
+}
+
 }  // namespace hgks
 
 // ===========================================================================
@@ -894,7 +956,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t qs, acc, B, F[3], metric[3][4], scal, part, qref, total;
+  size_t qs, acc, B, F[3], metric[3][4], scal, part, qref, mf, mpart, total;
   size_t nb_elems;  // elements of B (per direction maximum)
   int stat_blocks;
 };
@@ -933,6 +995,8 @@ Layout make_layout(const hgks_config& c) {
   L.stat_blocks = (int)((n3 + CELL_THREADS - 1) / CELL_THREADS);
   L.part = take(((size_t)L.stat_blocks + 1) * ST_COUNT * sizeof(double));
   L.qref = take(5 * sizeof(double));
+  L.mf = take(2 * sizeof(double));
+  L.mpart = take(((n3 + CELL_THREADS - 1) / CELL_THREADS) * sizeof(double));
   L.total = off;
   return L;
 }
@@ -978,6 +1042,8 @@ struct hgks_ctx_s {
   Scalars* sc;
   double* part;
   double* qref;
+  double* mf;     // mass-flux controller: {rho_b, m_t}
+  double* mpart;  // per-block sums of rho U dV (stage 2)
   hgks_status latched;
   double t0;
   std::string err;
@@ -1052,7 +1118,7 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
   if (!(c->cfl > 0.0)) return bad("cfl must be > 0");
   if (!(c->rho_ref > 0.0)) return bad("rho_ref must be > 0");
   if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return bad("unknown precision");
-  if (c->flags != 0) return bad("flags must be 0");
+  if ((c->flags & ~HGKS_FLAG_CONSTANT_MASS_FLUX) != 0) return bad("unknown flags");
   return HGKS_OK;
 }
 
@@ -1320,6 +1386,7 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
     P.bc[a] = cfg->bc[a];
     P.force[a] = cfg->body_force[a];
   }
+  P.flags = cfg->flags;
   P.gamma = cfg->gamma;
   P.gm1 = cfg->gamma - 1.0;
   P.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
@@ -1335,6 +1402,8 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   ctx->sc = reinterpret_cast<Scalars*>(ctx->ws + L.scal);
   ctx->part = reinterpret_cast<double*>(ctx->ws + L.part);
   ctx->qref = reinterpret_cast<double*>(ctx->ws + L.qref);
+  ctx->mf = reinterpret_cast<double*>(ctx->ws + L.mf);
+  ctx->mpart = reinterpret_cast<double*>(ctx->ws + L.mpart);
 
   // geometry: widths, d(index)/dx at faces, Gauss points and centres
   std::vector<double> host;
@@ -1366,19 +1435,25 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   }
   Scalars s0{};
   s0.t = t0;
+  s0.force_x = cfg->body_force[0];
   double qref[5] = {0, 0, 0, 0, 0};
   HIP_TRY(ctx, hipMemcpyAsync(ctx->sc, &s0, sizeof(Scalars), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->qref, qref, sizeof(qref), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   hipLaunchKernelGGL(wave_rate_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->sc);
-  if (precision_mixed(*cfg)) {
+  if (precision_mixed(*cfg) || (cfg->flags & HGKS_FLAG_CONSTANT_MASS_FLUX)) {
+    // volume means of the initial state: the mixed path's reference state,
+    // the mass-flux controller's target and mean density
     const int nb = ctx->L.stat_blocks;
     double* fin = ctx->part + (size_t)nb * ST_COUNT;
     double vol = 1.0;
     for (int a = 0; a < 3; ++a) vol *= cfg->hi[a] - cfg->lo[a];
     hipLaunchKernelGGL(stats_partial_kernel, dim3(nb), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, P, ctx->part);
     hipLaunchKernelGGL(stats_final_kernel, dim3(ST_COUNT), dim3(256), 0, ctx->stream, ctx->part, nb, fin);
-    hipLaunchKernelGGL(mean_state_kernel, dim3(1), dim3(64), 0, ctx->stream, fin, 1.0 / vol, ctx->qref);
+    if (precision_mixed(*cfg))
+      hipLaunchKernelGGL(mean_state_kernel, dim3(1), dim3(64), 0, ctx->stream, fin, 1.0 / vol, ctx->qref);
+    if (cfg->flags & HGKS_FLAG_CONSTANT_MASS_FLUX)
+      hipLaunchKernelGGL(mass_flux_init_kernel, dim3(1), dim3(64), 0, ctx->stream, fin, 1.0 / vol, ctx->mf, ctx->sc);
   }
   HIP_TRY(ctx, hipGetLastError());
   *out = ctx;
@@ -1397,14 +1472,22 @@ hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
     if (r != HGKS_OK) return r;
     HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
     hipLaunchKernelGGL(update_kernel<1>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
-                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc);
+                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
     HIP_TRY(ctx, prof_end(ctx));
     r = launch_fluxes_any(ctx, ctx->qs, 0);
     if (r != HGKS_OK) return r;
     HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
     hipLaunchKernelGGL(update_kernel<2>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
-                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc);
+                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
     HIP_TRY(ctx, prof_end(ctx));
+    if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX) {
+      double vol = 1.0;
+      for (int a = 0; a < 3; ++a) vol *= ctx->cfg.hi[a] - ctx->cfg.lo[a];
+      HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
+      hipLaunchKernelGGL(mass_flux_kernel, dim3(1), dim3(256), 0, ctx->stream, ctx->mpart, (int)cell_blocks(P),
+                         1.0 / vol, ctx->mf, ctx->sc);
+      HIP_TRY(ctx, prof_end(ctx));
+    }
     HIP_TRY(ctx, hipGetLastError());
   }
   return HGKS_OK;
@@ -1441,6 +1524,7 @@ hgks_status hgks_stats(hgks_ctx ctx, hgks_stats_t* out) {
   out->min_p = h[ST_MINP];
   out->min_rho = h[ST_MINR];
   out->nonfinite = h[ST_BAD] != 0.0 ? 1 : 0;
+  out->body_force_x = sc.force_x;
   if (out->nonfinite) ctx->latched = HGKS_E_NONFINITE;
   else if (!(out->min_p > 0.0) || !(out->min_rho > 0.0)) ctx->latched = HGKS_E_NEGATIVE_STATE;
   return HGKS_OK;
@@ -1463,7 +1547,7 @@ hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* 
   hgks_status r = launch_fluxes_any(ctx, q_dev, 1);
   if (r != HGKS_OK) return r;
   hipLaunchKernelGGL(residual_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, q_dev, ctx->F[0],
-                     ctx->F[1], ctx->F[2], P, L_dev, dL_dev);
+                     ctx->F[1], ctx->F[2], P, ctx->sc, L_dev, dL_dev);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return HGKS_OK;
@@ -1514,6 +1598,7 @@ hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t
   for (int i = 0; i < n; ++i) {
     if (validate(&cfgs[i], nullptr) != HGKS_OK) return HGKS_E_INVALID;
     if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
+    if (cfgs[i].flags != 0) return HGKS_E_UNSUPPORTED;
     total += align256(make_layout(cfgs[i]).total);
   }
   const std::vector<int> pre = batch_prefix(n, cfgs);
@@ -1528,7 +1613,8 @@ hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q
   if (!out) return HGKS_E_INVALID;
   *out = nullptr;
   size_t need = 0;
-  if (hgks_batch_workspace_size(n, cfgs, &need) != HGKS_OK) return HGKS_E_INVALID;
+  const hgks_status sz = hgks_batch_workspace_size(n, cfgs, &need);
+  if (sz != HGKS_OK) return sz;
   if (!q_devs || !ws_dev || ws_bytes < need || ((uintptr_t)ws_dev & 255u) != 0) return HGKS_E_INVALID;
   if (!hip_stream) return HGKS_E_INVALID;  // graph capture needs a created (non-default) stream
   for (int i = 0; i < n; ++i)

@@ -15,7 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhgks.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
+HGKS_FLAG_CONSTANT_MASS_FLUX = 1
 HGKS_OK, HGKS_E_INVALID, HGKS_E_NOMEM, HGKS_E_DEVICE, HGKS_E_NONFINITE, HGKS_E_NEGATIVE_STATE, HGKS_E_UNSUPPORTED = range(7)
 BC_PERIODIC, BC_ISOTHERMAL_WALL = 0, 1
 FP64, MIXED = 0, 1
@@ -65,6 +66,7 @@ class hgks_stats_t(ctypes.Structure):
         ("min_rho", ctypes.c_double),
         ("nonfinite", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
+        ("body_force_x", ctypes.c_double),
     ]
 
 
@@ -132,7 +134,7 @@ def make_config(p: dict, precision: int = FP64) -> hgks_config:
     c.cfl = float(p.get("cfl", 0.5))
     c.rho_ref = float(p.get("rho0", 1.0))
     c.precision = int(precision)
-    c.flags = 0
+    c.flags = HGKS_FLAG_CONSTANT_MASS_FLUX if p.get("mass_flux_control") else 0
     return c
 
 
@@ -170,6 +172,7 @@ def hgks_stats(ctx) -> dict:
         "t": s.t, "dt_last": s.dt_last, "steps": s.steps, "Ek": s.Ek, "eps_sol": s.eps_sol,
         "eps_dil": s.eps_dil, "eps_com": s.eps_com, "total": np.array(s.total[:]),
         "max_abs": np.array(s.max_abs[:]), "min_p": s.min_p, "min_rho": s.min_rho, "nonfinite": s.nonfinite,
+        "body_force_x": s.body_force_x,
     }
 
 

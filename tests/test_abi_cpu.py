@@ -51,7 +51,7 @@ def test_workspace_size_and_validation():
     # at least Q*, the accumulator and three face-flux buffers
     assert n >= 2 * 5 * 32 ** 3 * 8 + 3 * 10 * 33 * 32 * 32 * 8
     bad = [
-        ("abi_version", 99), ("precision", 7), ("flags", 1), ("gamma", 1.0), ("cfl", 0.0), ("prandtl", 0.0),
+        ("abi_version", 99), ("precision", 7), ("flags", 2), ("gamma", 1.0), ("cfl", 0.0), ("prandtl", 0.0),
         ("rho_ref", 0.0), ("mu_ref", -1.0),
     ]
     for field, val in bad:

@@ -125,3 +125,57 @@ def test_channel_wall_at_rest_stays_at_rest(hg):
     got = s.state()
     s.close()
     assert np.abs(got - q0).max() <= 1e-12 * np.abs(q0).max()
+
+
+def test_mass_flux_controller_deadbeat_gpu(hg):
+    """Constant-mass-flux flag on a periodic uniform flow (no wall drag): the
+    force answers -f0 after one step and 0 after two, and the mean streamwise
+    momentum returns to its initial value."""
+    n = (8, 6, 5)
+    p = W.tgv_params(n, ma=0.3, re=100.0)
+    p["body_force"] = (0.02, 0.0, 0.0)
+    p["mass_flux_control"] = True
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.2), f(0.3), f(-0.1), f(0.2), f(2.0)))
+    s = hg.Solver(p, q0)
+    s.step(1, 0.01)
+    f1 = s.stats()["body_force_x"]
+    s.step(1, 0.01)
+    st = s.stats()
+    got = s.state()
+    s.close()
+    say("deadbeat forces", f1, st["body_force_x"])
+    assert abs(f1 + 0.02) <= 1e-12 and abs(st["body_force_x"]) <= 1e-12
+    assert abs(got[1].mean() - q0[1].mean()) <= 1e-14 * abs(q0[1].mean())
+
+
+def test_channel_mass_flux_parity(hg, oracle):
+    """Channel with the constant-mass-flux controller, 5 CFL steps: state to
+    1e-11 of each component's max against the oracle.  The controller's force
+    is a difference of volume means divided by rho_b dt; the two sides sum the
+    N cells in different orders, so after k steps the forces agree to within
+    3 k N u max|rho U| / (rho_b dt) (u = 2^-53)."""
+    p, q = channel_case((16, 24, 12))
+    p["mass_flux_control"] = True
+    s = hg.Solver(p, q)
+    s.step(5, 0.0)
+    got = s.state()
+    st = s.stats()
+    s.close()
+    ref, dt_last, f_ref = oracle.step_force(p, q, 5, 0.0)
+    err = rel_err(got, ref)
+    ncell = 16 * 24 * 12
+    tol_f = 3 * 5 * ncell * 2.0 ** -53 * np.abs(q[1]).max() / (1.0 * 0.9 * dt_last)
+    say("channel mass-flux 5 steps err", err, "force", st["body_force_x"], f_ref, "tol", tol_f)
+    assert (err <= 1e-11).all()
+    assert abs(st["body_force_x"] - f_ref) <= tol_f
+
+
+def test_batch_rejects_mass_flux_flag(hg):
+    p, _ = channel_case((8, 16, 8))
+    p["mass_flux_control"] = True
+    cfg = hg.make_config(p)
+    with pytest.raises(hg.HGKSError) as e:
+        hg.hgks_batch_workspace_size([cfg])
+    assert e.value.status == hg.HGKS_E_UNSUPPORTED

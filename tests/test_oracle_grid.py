@@ -227,3 +227,51 @@ def test_channel_poiseuille_force_balance(oracle):
     p["body_force"] = (0.0, 0.0, 0.0)
     L0, _ = oracle.residual(p, q, 1e-3)
     np.testing.assert_allclose(L0[1][:, 8:-8, :], -rho0 * fx, rtol=0.02)
+
+
+def test_mass_flux_controller_deadbeat_on_uniform_flow(oracle):
+    """Constant-mass-flux controller (R24) on a periodic uniform flow: no wall
+    drag, so the momentum changes by exactly dt rho f per step (the flux
+    divergence vanishes and dS/dt has no streamwise part).  From f0 the
+    controller must answer -f0 after one step and 0 after two, with the mean
+    streamwise momentum back at its initial value."""
+    n = (8, 6, 5)
+    p = W.tgv_params(n, ma=0.3, re=100.0)
+    p["body_force"] = (0.02, 0.0, 0.0)
+    p["mass_flux_control"] = True
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.2), f(0.3), f(-0.1), f(0.2), f(2.0)))
+    dt = 0.01
+    q1, _, f1 = oracle.step_force(p, q0, 1, dt)
+    assert q1[1].mean() == pytest.approx(q0[1].mean() + dt * 1.2 * 0.02, rel=1e-14)
+    assert f1 == pytest.approx(-0.02, rel=1e-12)
+    q2, _, f2 = oracle.step_force(p, q0, 2, dt)
+    assert abs(f2) <= 1e-12
+    assert q2[1].mean() == pytest.approx(q0[1].mean(), rel=1e-14)
+
+
+def test_mass_flux_controller_holds_channel_momentum(oracle):
+    """On a walled channel the controller keeps the volume-mean streamwise
+    momentum at its target (to 1e-7 after 8 steps) while the constant force of
+    Dean's correlation lets it drift, and its force approaches the laminar
+    balance with the Poiseuille wall shear."""
+    p = W.channel_params((12, 16, 8), ma_b=0.5, re_b=3000.0)
+    q0 = W.channel_initial(p, seed=2207)
+    # physical cell heights from the tanh map of the cell edges (Sec. 4.2)
+    ny, b, lo, hi = p["n"][1], p["y_stretch"], p["lo"][1], p["hi"][1]
+    xi = np.arange(ny + 1) / ny
+    edges = lo + 0.5 * (hi - lo) * (1.0 + np.tanh(b * (2.0 * xi - 1.0)) / math.tanh(b))
+    hy = np.diff(edges)
+    mean_m = lambda q: float((q[1].mean(axis=(0, 2)) * hy).sum() / hy.sum())
+    m0 = mean_m(q0)
+    q_free, _ = oracle.step(p, q0, 8, 0.0)
+    pc = dict(p, mass_flux_control=True)
+    q_ctl, _, f = oracle.step_force(pc, q0, 8, 0.0)
+    drift_free = abs(mean_m(q_free) - m0)
+    drift_ctl = abs(mean_m(q_ctl) - m0)
+    assert drift_ctl < 1e-3 * drift_free and drift_ctl < 1e-7 * abs(m0), (drift_ctl, drift_free)
+    # the force settles at the laminar balance with the wall shear of the
+    # Poiseuille profile, f = 3 mu U_b / h^2 (h = 1, U_b = 1)
+    f_lam = 3.0 * p["mu_ref"] * 1.0
+    assert abs(f - f_lam) < 0.03 * f_lam, (f, f_lam)
