@@ -136,7 +136,7 @@ def ensemble_bench(steps: int, precision: str) -> dict:
     }
 
 
-def tgv_history(n: int, ma: float, t_end: float, every: int) -> dict:
+def tgv_history(n: int, ma: float, t_end: float, every: int, with_mixed: bool = True) -> dict:
     """TGV at n^3 (Re 1600, Pr 0.72, CFL 0.5) advanced to t_end by the FP64
     and the mixed path in lockstep, the mixed path on the FP64 run's time
     steps so the two are compared at matched steps: E_k and eps_com every
@@ -150,30 +150,39 @@ def tgv_history(n: int, ma: float, t_end: float, every: int) -> dict:
     p = W.tgv_params(n, ma=ma, re=1600.0, pr=0.72, cfl=0.5)
     q0 = W.tgv_initial(p)
     s64 = hgks.Solver(p, q0, precision=hgks.FP64)
-    smx = hgks.Solver(p, q0, precision=hgks.MIXED)
+    smx = hgks.Solver(p, q0, precision=hgks.MIXED) if with_mixed else None
     keys = ("step", "t", "Ek_fp64", "eps_com_fp64", "Ek_mixed", "eps_com_mixed")
     hist = {k: [] for k in keys}
     marks = [m for m in (1.0, 2.0, 5.0, 10.0) if m <= t_end]
     at_marks = []
 
     def record(step, st64, stmx):
-        for k, v in zip(keys, (step, st64["t"], st64["Ek"], st64["eps_com"], stmx["Ek"], stmx["eps_com"])):
+        for k, v in zip(keys, (step, st64["t"], st64["Ek"], st64["eps_com"],
+                               stmx["Ek"] if stmx else None, stmx["eps_com"] if stmx else None)):
             hist[k].append(v)
 
-    record(0, s64.stats(), smx.stats())
+    record(0, s64.stats(), smx.stats() if smx else None)
     step, t = 0, 0.0
     w0 = time.perf_counter()
     while t < t_end:
         s64.step(1, 0.0)
         st64 = s64.stats()
-        smx.step(1, st64["dt_last"])
+        if st64["nonfinite"] or not (st64["min_p"] > 0):
+            print(f"# FP64 state invalid at step {step + 1} (t = {st64['t']:.4f})", file=sys.stderr, flush=True)
+            hist["failed_at_step"] = step + 1
+            break
+        if smx:
+            smx.step(1, st64["dt_last"])
         step += 1
         t = st64["t"]
         hit = bool(marks) and t >= marks[0]
+        stmx = None
         if step % every == 0 or hit or t >= t_end:
-            stmx = smx.stats()
+            stmx = smx.stats() if smx else None
             record(step, st64, stmx)
-        if hit:
+        if hit and not smx:
+            marks.pop(0)
+        elif hit:
             a, b = s64.q, smx.q
             rel = ((b - a).abs().amax(dim=(1, 2, 3)) / a.abs().amax(dim=(1, 2, 3))).tolist()
             mom = float((b[1:4] - a[1:4]).abs().max() / a[1:4].pow(2).sum(dim=0).sqrt().max())
@@ -188,13 +197,64 @@ def tgv_history(n: int, ma: float, t_end: float, every: int) -> dict:
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     s64.close()
-    smx.close()
-    return {"metric": f"TGV {n}^3 E_k and eps_com histories, FP64 and mixed at matched steps",
+    if smx:
+        smx.close()
+    return {"metric": f"TGV {n}^3 E_k and eps_com histories, FP64" + (" and mixed at matched steps" if smx else ""),
             "n": n, "ma": ma, "re": 1600.0, "steps": step, "t_end": t, "every": every,
             "wall_s": wall, "mixed_vs_fp64": at_marks, "history": hist}
 
 
-def channel_run(n: int, t_end: float, every: int) -> dict:
+def channel_statistics(q, p: dict, y) -> dict:
+    """x-z plane statistics of a channel state q [5, nz, ny, nx] (torch
+    tensor, any device; y the cell-centre heights): Favre-averaged U and T,
+    rms of the Favre fluctuations u'', v'', w'', T'', the shear stress
+    <rho u'' v''>/<rho>, the turbulent Mach number sqrt(<rho |u''|^2>/<rho>) / <c>,
+    and the lower wall's scaling: tau_w (one-sided quadratic through the
+    no-slip wall point), rho_w = p_1 / T_w, u_tau, Re_tau = rho_w u_tau h / mu_w
+    (h = 1), y+ and the van Driest velocity U_VD+ = int_0^{U+} sqrt(<rho>/rho_w) dU+
+    (trapezoids from the wall), for the cells of the lower half."""
+    import torch
+
+    gm1, gamma = p["gamma"] - 1.0, p["gamma"]
+    mu_w, T_w, lo = p["mu_ref"], p["T_wall"], p["lo"][1]
+    rho = q[0]
+    vel = [q[1] / rho, q[2] / rho, q[3] / rho]
+    pres = gm1 * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / rho)
+    T = pres / rho
+    mean = lambda a: a.mean(dim=(0, 2))
+    rb = mean(rho)
+    fav = lambda a: mean(rho * a) / rb
+    plane = lambda prof: prof[None, :, None]
+    Uf = [fav(u) for u in vel]
+    Tf = fav(T)
+    fl = [u - plane(m) for u, m in zip(vel, Uf)]
+    Tfl = T - plane(Tf)
+    rms = [torch.sqrt(fav(f * f)) for f in fl]
+    c = torch.sqrt(gamma * pres / rho)
+    Mt = torch.sqrt(fav(fl[0] ** 2 + fl[1] ** 2 + fl[2] ** 2)) / mean(c)
+    y = torch.as_tensor(y, dtype=q.dtype, device=q.device)
+    d1, d2 = float(y[0] - lo), float(y[1] - lo)
+    u1, u2 = float(Uf[0][0]), float(Uf[0][1])
+    tau_w = mu_w * (u1 * d2 * d2 - u2 * d1 * d1) / (d1 * d2 * (d2 - d1))
+    rho_w = float(mean(pres)[0]) / T_w
+    u_tau = math.sqrt(abs(tau_w) / rho_w)
+    nu_w = mu_w / rho_w
+    half = int((y < 0.5 * (lo + p["hi"][1])).sum())
+    yp = (y[:half] - lo) * u_tau / nu_w
+    Up = Uf[0][:half] / u_tau
+    wgt = torch.sqrt(rb[:half] / rho_w)
+    # trapezoids from the wall point (U+ = 0, density weight 1 at the wall)
+    w_prev = torch.cat([torch.ones(1, dtype=q.dtype, device=q.device), wgt[:-1]])
+    U_prev = torch.cat([torch.zeros(1, dtype=q.dtype, device=q.device), Up[:-1]])
+    U_vd = torch.cumsum(0.5 * (wgt + w_prev) * (Up - U_prev), dim=0)
+    L = lambda a: [float(v) for v in a[:half]]
+    return {"tau_w": tau_w, "rho_w": rho_w, "u_tau": u_tau, "Re_tau": rho_w * u_tau / mu_w,
+            "y": L(y), "y_plus": L(yp), "U": L(Uf[0]), "U_plus": L(Up), "U_vd_plus": L(U_vd), "T": L(Tf),
+            "u_rms": L(rms[0]), "v_rms": L(rms[1]), "w_rms": L(rms[2]),
+            "T_rms": L(torch.sqrt(fav(Tfl * Tfl))), "uv": L(fav(fl[0] * fl[1])), "M_t": L(Mt)}
+
+
+def channel_run(n: int, t_end: float, every: int, mass_flux: bool = False) -> dict:
     """Turbulent channel (2 pi x 2 x pi, n^3, tanh-stretched y, isothermal
     walls, Ma_b 0.5, Re_b 3000, constant body force, Poiseuille + 10% noise)
     advanced to t_end by the FP64 and the mixed path in lockstep (the mixed
@@ -208,6 +268,7 @@ def channel_run(n: int, t_end: float, every: int) -> dict:
     from paper_2207_01173_amd import workloads as W
 
     p = W.channel_params((n, n, n), ma_b=0.5, re_b=3000.0)
+    p["mass_flux_control"] = mass_flux
     q0 = W.channel_initial(p, seed=2207)
     y = torch.as_tensor(W.channel_y_centres(p), dtype=torch.float64, device="cuda")
     ylo, yhi = p["lo"][1], p["hi"][1]
@@ -241,13 +302,15 @@ def channel_run(n: int, t_end: float, every: int) -> dict:
 
     s64 = hgks.Solver(p, q0, precision=hgks.FP64)
     smx = hgks.Solver(p, q0, precision=hgks.MIXED)
-    hist = {k: [] for k in ("step", "t", "tau_w_fp64", "tau_w_mixed", "U_b_fp64", "U_b_mixed")}
+    hist = {k: [] for k in ("step", "t", "tau_w_fp64", "tau_w_mixed", "U_b_fp64", "U_b_mixed", "force_fp64",
+                            "force_mixed")}
 
     def record(step, t):
         _, U64, _ = means(s64.q)
         _, Umx, _ = means(smx.q)
         for k, v in (("step", step), ("t", t), ("tau_w_fp64", wall_shear(U64)), ("tau_w_mixed", wall_shear(Umx)),
-                     ("U_b_fp64", bulk(s64.q)), ("U_b_mixed", bulk(smx.q))):
+                     ("U_b_fp64", bulk(s64.q)), ("U_b_mixed", bulk(smx.q)),
+                     ("force_fp64", s64.stats()["body_force_x"]), ("force_mixed", smx.stats()["body_force_x"])):
             hist[k].append(v)
         print(f"# step {step} t={t:.4f} tau_w fp64 {hist['tau_w_fp64'][-1]} mixed {hist['tau_w_mixed'][-1]} "
               f"U_b {hist['U_b_fp64'][-1]:.6f} {hist['U_b_mixed'][-1]:.6f} ({time.perf_counter() - w0:.0f} s)",
@@ -273,9 +336,11 @@ def channel_run(n: int, t_end: float, every: int) -> dict:
     a, b = s64.q, smx.q
     rel = ((b - a).abs().amax(dim=(1, 2, 3)) / a.abs().amax(dim=(1, 2, 3))).tolist()
     stmx = smx.stats()
+    stats = {"fp64": channel_statistics(s64.q, p, y), "mixed": channel_statistics(smx.q, p, y)}
     s64.close()
     smx.close()
-    return {"metric": f"channel {n}^3 (Ma_b 0.5, Re_b 3000): wall shear and mean profiles, FP64 and mixed",
+    return {"statistics": stats, "metric": f"channel {n}^3 (Ma_b 0.5, Re_b 3000, " + ("constant mass flux" if mass_flux else "constant force")
+            + "): wall shear and mean profiles, FP64 and mixed",
             "n": n, "steps": step, "t_end": t, "wall_s": wall, "every": every,
             "mixed_nonfinite": stmx["nonfinite"], "mixed_vs_fp64_state_rel_maxnorm": rel,
             "profiles": {"y": y.tolist(), "U_fp64": U64.tolist(), "U_mixed": Umx.tolist(),
@@ -330,6 +395,7 @@ def main() -> int:
                     help="instead: TGV --n^3 at Ma --ma to t = T_END, FP64 and mixed histories")
     ap.add_argument("--channel", type=float, default=0.0, metavar="T_END",
                     help="instead: channel at --n^3 to t = T_END, FP64 and mixed wall shear and profiles")
+    ap.add_argument("--mass-flux", action="store_true", help="--channel with the constant-mass-flux controller")
     ap.add_argument("--ma", type=float, default=0.1, help="Mach number of --history")
     ap.add_argument("--every", type=int, default=10, help="statistics interval of --history (steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -354,10 +420,10 @@ def main() -> int:
         print(json.dumps(ensemble_bench(args.steps, args.precision)), flush=True)
         return 0
     if args.channel > 0:
-        print(json.dumps(channel_run(args.n, args.channel, args.every)), flush=True)
+        print(json.dumps(channel_run(args.n, args.channel, args.every, args.mass_flux)), flush=True)
         return 0
     if args.history > 0:
-        print(json.dumps(tgv_history(args.n, args.ma, args.history, args.every)), flush=True)
+        print(json.dumps(tgv_history(args.n, args.ma, args.history, args.every, not args.no_mixed)), flush=True)
         return 0
     n = args.n
     p = tgv_workload(n)
