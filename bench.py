@@ -45,9 +45,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "e8198c15ec35b422508ea12bca7cdb96414ee57ec780ad28bd55e59497861ea2",
-    "fetch_bytes": 1.0191e+10,
-    "write_bytes": 3.0509e+09,
+    "sources_sha256": "50f8e1241de166d5addb3b29d5c8ee3cd14399fa0171961f5889641b8df3337a",
+    "fetch_bytes": 1.0154e+10,
+    "write_bytes": 3.1605e+09,
 }
 
 # MI355X published peaks
