@@ -84,3 +84,33 @@ def test_status_strings():
     for s in range(7):
         assert L.hgks_status_string(s)
     assert L.hgks_status_string(42) == b"unknown status"
+
+
+def test_largest_grids():
+    """The flux kernel addresses one quantity's two Gauss lines of buffer B with
+    32-bit byte offsets: 2 x 8 x pitch(n_x + 1) x n_y x n_z must stay below
+    2^32 (pitch = x extent rounded up to 32).  630^3 fits (640 x 630 x 630),
+    640^3 does not (672 x 640 x 640); 512^3 is well inside."""
+    for n, ok in ((512, True), (630, True), (640, False)):
+        c = hgks.make_config(W.tgv_params(n))
+        if ok:
+            assert hgks.hgks_workspace_size(c) > 0
+        else:
+            with pytest.raises(hgks.HGKSError) as e:
+                hgks.hgks_workspace_size(c)
+            assert e.value.status == hgks.HGKS_E_INVALID
+
+
+def test_batch_rejects_unsupported_members():
+    """Batched members must share one precision and use no flags."""
+    ens = [W.tgv_params(12), W.tgv_params((16, 12, 8))]
+    cfgs = [hgks.make_config(p) for p in ens]
+    assert hgks.hgks_batch_workspace_size(cfgs) > 0
+    mixed = [hgks.make_config(ens[0]), hgks.make_config(ens[1], hgks.MIXED)]
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.hgks_batch_workspace_size(mixed)
+    assert e.value.status == hgks.HGKS_E_INVALID
+    flagged = [hgks.make_config(dict(ens[0], mass_flux_control=True)), cfgs[1]]
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.hgks_batch_workspace_size(flagged)
+    assert e.value.status == hgks.HGKS_E_UNSUPPORTED
