@@ -387,7 +387,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run beside FP64")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed and FP32 runs beside FP64")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--ensemble", action="store_true",
                     help="measure the 64-instance ensemble (batched vs per-instance loop) instead")
@@ -432,7 +432,7 @@ def main() -> int:
 
     def run(prec_name: str):
         """Warmup, then K timed CFL steps with per-kernel event timing."""
-        prec = hgks.FP64 if prec_name == "fp64" else hgks.MIXED
+        prec = {"fp64": hgks.FP64, "mixed": hgks.MIXED, "fp32": hgks.FP32}[prec_name]
         solver = hgks.Solver(p, q0, precision=prec)
         print(f"# {prec_name}: warmup {args.warmup} steps", file=sys.stderr, flush=True)
         solver.step(args.warmup, 0.0)
@@ -499,24 +499,27 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_mixed:
-        m_elapsed, m_roof, m_st, state_m = run("mixed")
-        # stated error of the mixed path against the FP64 path at matched steps
-        rel = (abs(state_m - state64).max(axis=(1, 2, 3)) / abs(state64).max(axis=(1, 2, 3)))
-        mom = abs(state_m[1:4] - state64[1:4]).max() / ((state64[1:4] ** 2).sum(axis=0) ** 0.5).max()
-        out["mixed"] = {
-            "value": cell_stages / m_elapsed,
-            "ms_per_step": m_elapsed / args.steps * 1e3,
-            "speedup_vs_fp64": elapsed / m_elapsed,
-            "dtype": "f32 reconstruction and flux on deviations from the mean state, f64 state/update/reductions",
-            "error_vs_fp64": {
-                "after_steps": args.warmup + args.steps,
-                "state_rel_maxnorm": [float(x) for x in rel],
-                "momentum_rel_to_max_speed": float(mom),
-                "Ek_rel": abs(m_st["Ek"] - st["Ek"]) / st["Ek"],
-                "eps_com_rel": abs(m_st["eps_com"] - st["eps_com"]) / st["eps_com"],
-            },
-            "roofline": m_roof,
-        }
+        dtypes = {"mixed": "f32 reconstruction and flux on deviations from the mean state, f64 state/update/reductions",
+                  "fp32": "f32 state, stages and update, f32 reconstruction and flux, f64 face fluxes and reductions"}
+        for name in ("mixed", "fp32"):
+            m_elapsed, m_roof, m_st, state_m = run(name)
+            # stated error of the reduced-precision path against the FP64 path at matched steps
+            rel = (abs(state_m - state64).max(axis=(1, 2, 3)) / abs(state64).max(axis=(1, 2, 3)))
+            mom = abs(state_m[1:4] - state64[1:4]).max() / ((state64[1:4] ** 2).sum(axis=0) ** 0.5).max()
+            out[name] = {
+                "value": cell_stages / m_elapsed,
+                "ms_per_step": m_elapsed / args.steps * 1e3,
+                "speedup_vs_fp64": elapsed / m_elapsed,
+                "dtype": dtypes[name],
+                "error_vs_fp64": {
+                    "after_steps": args.warmup + args.steps,
+                    "state_rel_maxnorm": [float(x) for x in rel],
+                    "momentum_rel_to_max_speed": float(mom),
+                    "Ek_rel": abs(m_st["Ek"] - st["Ek"]) / st["Ek"],
+                    "eps_com_rel": abs(m_st["eps_com"] - st["eps_com"]) / st["eps_com"],
+                },
+                "roofline": m_roof,
+            }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

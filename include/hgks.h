@@ -69,7 +69,14 @@ typedef enum {
 } hgks_status;
 
 enum { HGKS_BC_PERIODIC = 0, HGKS_BC_ISOTHERMAL_WALL = 1 }; /* wall: y axis only */
-enum { HGKS_FP64 = 0, HGKS_MIXED = 1 };
+/* Precision of a context.  FP64: everything in FP64.  MIXED: reconstruction
+ * and Gauss-point flux in FP32 on deviations from the initial state's volume
+ * mean, state, update and reductions FP64.  FP32: additionally the state, Q*
+ * and the S2O4 accumulator in FP32 (an FP32 working copy; hgks_step reads the
+ * caller's FP64 state when it starts and writes it back when it ends), the
+ * face fluxes and reductions staying FP64; the whole-code FP32 point of the
+ * paper's precision comparison (Sec. 4.2).  Batched contexts: FP64 or MIXED. */
+enum { HGKS_FP64 = 0, HGKS_MIXED = 1, HGKS_FP32 = 2 };
 
 typedef struct {
   int32_t abi_version;   /* must equal HGKS_ABI_VERSION */
@@ -84,7 +91,7 @@ typedef struct {
   double body_force[3];  /* constant acceleration (source in L) */
   double cfl;            /* CFL number of the time-step rule when dt is not fixed */
   double rho_ref;        /* rho0 of the statistics normalisation (> 0) */
-  int32_t precision;     /* HGKS_FP64 or HGKS_MIXED */
+  int32_t precision;     /* HGKS_FP64, HGKS_MIXED or HGKS_FP32 */
   int32_t flags;         /* 0 or HGKS_FLAG_CONSTANT_MASS_FLUX */
 } hgks_config;
 

@@ -113,7 +113,8 @@ __host__ __device__ inline void b_extents(const Params& P, int d, int be[3], int
 // One cell of the padded state, synthesised from the interior: periodic wrap,
 // or the isothermal-wall mirror (velocity reversed, same pressure,
 // temperature 2 T_w - T (not below 0.1 T_w), density p/T), all in FP64.
-__device__ __forceinline__ void load_cell(const double* __restrict__ q, const Params& P, int c0, int c1, int c2,
+template <class S>
+__device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params& P, int c0, int c1, int c2,
                                           double v[5]) {
   int c[3] = {c0, c1, c2};
   bool mirror = false;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void load_cell(const double* __restrict__ q, const Pa
   const size_t n3 = cells(P);
   const size_t idx = ((size_t)c[2] * P.n[1] + c[1]) * P.n[0] + c[0];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) v[k] = gmem(q)[k * n3 + idx];
+  for (int k = 0; k < 5; ++k) v[k] = double(gmem(q)[k * n3 + idx]);
   if (mirror) {
     double rho = v[0], ir = 1.0 / rho;
     double U = v[1] * ir, V = v[2] * ir, W = v[3] * ir;
@@ -176,8 +177,8 @@ template <int DIR> __host__ __device__ inline int recon_tiles(const Params& P) {
   return ((be[0] + S[0] - 1) / S[0]) * ((be[1] + S[1] - 1) / S[1]) * ((be[2] + S[2] - 1) / S[2]);
 }
 
-template <int DIR, class R>
-__device__ __forceinline__ void recon_tile(const double* __restrict__ q, const Params& P,
+template <int DIR, class R, class ST = double>
+__device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Params& P,
                                            const double* __restrict__ qref, R* __restrict__ B, int lin,
                                            R (*A)[recon_lds_faces<DIR>()]) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
@@ -302,12 +303,12 @@ __device__ __forceinline__ void recon_tile(const double* __restrict__ q, const P
   }
 }
 
-template <int DIR, class R>
-__global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const double* __restrict__ q, Params P,
+template <int DIR, class R, class ST>
+__global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const ST* __restrict__ q, Params P,
                                                               const double* __restrict__ qref,
                                                               R* __restrict__ B) {
   __shared__ R A[25][recon_lds_faces<DIR>()];
-  recon_tile<DIR, R>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR>(P)), A);
+  recon_tile<DIR, R, ST>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR>(P)), A);
 }
 
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
@@ -527,7 +528,8 @@ __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_kernel(con
 
 // L and dL/dt of one cell from the six face fluxes, plus the body-force source
 // S = (0, rho f, m . f) and its time derivative (0, f L_rho, f . L_m).
-__device__ __forceinline__ void cell_residual(const double* __restrict__ qe, const double* __restrict__ F0,
+template <class S>
+__device__ __forceinline__ void cell_residual(const S* __restrict__ qe, const double* __restrict__ F0,
                                               const double* __restrict__ F1, const double* __restrict__ F2,
                                               const Params& P, const double fb[3], int i, int j, int k, double L[5],
                                               double dL[5]) {
@@ -552,7 +554,7 @@ __device__ __forceinline__ void cell_residual(const double* __restrict__ qe, con
       dL[m] -= (Fd[d][(5 + m) * NF + fp] - Fd[d][(5 + m) * NF + fm]) / vol;
     }
   }
-  const HGKS_GLOBAL double* qg = gmem(qe);
+  const HGKS_GLOBAL S* qg = gmem(qe);
   const double rho = qg[c], mx = qg[n3 + c], my = qg[2 * n3 + c], mz = qg[3 * n3 + c];
   const double lrho = L[0];
   L[1] += rho * fb[0];
@@ -612,16 +614,16 @@ __device__ __forceinline__ void block_sum_store(double x, double* dst) {
 constexpr int CELL_THREADS = 256;
 
 // S2O4 stage for cell block `blk` (CELL_THREADS cells) of one instance.
-template <int STAGE>
-__device__ __forceinline__ void update_block(double* __restrict__ q, double* __restrict__ qs, double* __restrict__ acc,
+template <int STAGE, class S = double>
+__device__ __forceinline__ void update_block(S* __restrict__ q, S* __restrict__ qs, S* __restrict__ acc,
                                              const double* __restrict__ F0, const double* __restrict__ F1,
                                              const double* __restrict__ F2, const Params& P, Scalars* __restrict__ sc,
                                              double* __restrict__ mpart, size_t blk) {
   const size_t n3 = cells(P);
   const size_t c = blk * CELL_THREADS + threadIdx.x;
-  HGKS_GLOBAL double* qg = gmem(q);
-  HGKS_GLOBAL double* qsg = gmem(qs);
-  HGKS_GLOBAL double* accg = gmem(acc);
+  HGKS_GLOBAL S* qg = gmem(q);
+  HGKS_GLOBAL S* qsg = gmem(qs);
+  HGKS_GLOBAL S* accg = gmem(acc);
   const double fb[3] = {gmem(sc)->force_x, P.force[1], P.force[2]};
   double rate = 0.0, mflux = 0.0;
   if (c < n3) {
@@ -635,16 +637,16 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const double qn = qg[m * n3 + c];
-        qsg[m * n3 + c] = qn + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m];
-        accg[m * n3 + c] = qn + dt * L[m] + dt * dt / 6.0 * dL[m];
+        qsg[m * n3 + c] = S(qn + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m]);
+        accg[m * n3 + c] = S(qn + dt * L[m] + dt * dt / 6.0 * dL[m]);
       }
     } else {
       cell_residual(qs, F0, F1, F2, P, fb, i, j, k, L, dL);
       double v[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        v[m] = accg[m * n3 + c] + dt * dt / 3.0 * dL[m];
-        qg[m * n3 + c] = v[m];
+        v[m] = double(S(double(accg[m * n3 + c]) + dt * dt / 3.0 * dL[m]));
+        qg[m * n3 + c] = S(v[m]);
       }
       rate = cell_wave_rate(v, P, i, j, k);
       if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX)
@@ -657,13 +659,13 @@ __device__ __forceinline__ void update_block(double* __restrict__ q, double* __r
   }
 }
 
-template <int STAGE>
-__global__ __launch_bounds__(CELL_THREADS) void update_kernel(double* __restrict__ q, double* __restrict__ qs,
-                                                              double* __restrict__ acc, const double* __restrict__ F0,
+template <int STAGE, class S>
+__global__ __launch_bounds__(CELL_THREADS) void update_kernel(S* __restrict__ q, S* __restrict__ qs,
+                                                              S* __restrict__ acc, const double* __restrict__ F0,
                                                               const double* __restrict__ F1,
                                                               const double* __restrict__ F2, Params P,
                                                               Scalars* __restrict__ sc, double* __restrict__ mpart) {
-  update_block<STAGE>(q, qs, acc, F0, F1, F2, P, sc, mpart, blockIdx.x);
+  update_block<STAGE, S>(q, qs, acc, F0, F1, F2, P, sc, mpart, blockIdx.x);
 }
 
 __global__ __launch_bounds__(CELL_THREADS) void residual_kernel(const double* __restrict__ qe,
@@ -719,6 +721,13 @@ __global__ void begin_step_kernel(Scalars* sc, double cfl, double dt_fixed) {
 
 __global__ void set_scalar_kernel(double* dst, double v) {
   if (threadIdx.x == 0) *dst = v;
+}
+
+// Element-wise precision conversion (the FP32 path's working copy of the state).
+template <class A, class Bt>
+__global__ __launch_bounds__(CELL_THREADS) void convert_kernel(const A* __restrict__ a, Bt* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  if (i < n) gmem(b)[i] = Bt(gmem(a)[i]);
 }
 
 // ---- statistics ----------------------------------------------------------
@@ -956,12 +965,15 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t qs, acc, B, F[3], metric[3][4], scal, part, qref, mf, mpart, total;
+  size_t qs, acc, B, F[3], metric[3][4], scal, part, qref, mf, mpart, q32, total;
   size_t nb_elems;  // elements of B (per direction maximum)
   int stat_blocks;
 };
 
-bool precision_mixed(const hgks_config& c) { return c.precision == HGKS_MIXED; }
+// FP32 reconstruction and flux (the mixed and the FP32 paths).
+bool precision_mixed(const hgks_config& c) { return c.precision == HGKS_MIXED || c.precision == HGKS_FP32; }
+// The state, stage values and update in FP32 as well.
+bool precision_fp32(const hgks_config& c) { return c.precision == HGKS_FP32; }
 
 Layout make_layout(const hgks_config& c) {
   Params P{};
@@ -997,6 +1009,7 @@ Layout make_layout(const hgks_config& c) {
   L.qref = take(5 * sizeof(double));
   L.mf = take(2 * sizeof(double));
   L.mpart = take(((n3 + CELL_THREADS - 1) / CELL_THREADS) * sizeof(double));
+  L.q32 = precision_fp32(c) ? take(5 * n3 * sizeof(float)) : 0;  // FP32 path: working copy of the state
   L.total = off;
   return L;
 }
@@ -1042,6 +1055,7 @@ struct hgks_ctx_s {
   Scalars* sc;
   double* part;
   double* qref;
+  float* q32;     // FP32 path: working copy of the state (Q* and the accumulator reuse qs, acc)
   double* mf;     // mass-flux controller: {rho_b, m_t}
   double* mpart;  // per-block sums of rho U dV (stage 2)
   hgks_status latched;
@@ -1117,7 +1131,8 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
   if (!(c->y_stretch >= 0.0)) return bad("y_stretch must be >= 0");
   if (!(c->cfl > 0.0)) return bad("cfl must be > 0");
   if (!(c->rho_ref > 0.0)) return bad("rho_ref must be > 0");
-  if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return bad("unknown precision");
+  if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED && c->precision != HGKS_FP32)
+    return bad("unknown precision");
   if ((c->flags & ~HGKS_FLAG_CONSTANT_MASS_FLUX) != 0) return bad("unknown flags");
   return HGKS_OK;
 }
@@ -1131,8 +1146,8 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
     }                                                                                    \
   } while (0)
 
-template <class R>
-static hgks_status launch_fluxes(hgks_ctx ctx, const double* qin, int use_residual_dt) {
+template <class R, class S>
+static hgks_status launch_fluxes(hgks_ctx ctx, const S* qin, int use_residual_dt) {
   const Params& P = ctx->P;
   R* B = static_cast<R*>(ctx->B);
   const double* qref = ctx->qref;
@@ -1142,7 +1157,7 @@ static hgks_status launch_fluxes(hgks_ctx ctx, const double* qin, int use_residu
   auto flux_blocks = [&](int d) { return (unsigned)flux_tiles<16>(P, d); };
 #define HGKS_DIRECTION(D)                                                                                    \
   HIP_TRY(ctx, prof_begin(ctx, PROF_RECON));                                                                 \
-  hipLaunchKernelGGL((recon_kernel<D, R>), dim3(recon_blocks(D)), dim3(RECON_THREADS), 0,                    \
+  hipLaunchKernelGGL((recon_kernel<D, R, S>), dim3(recon_blocks(D)), dim3(RECON_THREADS), 0,                 \
                      ctx->stream, qin, P, qref, B);                                                          \
   HIP_TRY(ctx, prof_end(ctx));                                                                               \
   HIP_TRY(ctx, prof_begin(ctx, PROF_FLUX));                                                                  \
@@ -1158,11 +1173,46 @@ static hgks_status launch_fluxes(hgks_ctx ctx, const double* qin, int use_residu
 }
 
 static hgks_status launch_fluxes_any(hgks_ctx ctx, const double* qin, int use_residual_dt) {
-  if (precision_mixed(ctx->cfg)) return launch_fluxes<float>(ctx, qin, use_residual_dt);
-  return launch_fluxes<double>(ctx, qin, use_residual_dt);
+  if (precision_mixed(ctx->cfg)) return launch_fluxes<float, double>(ctx, qin, use_residual_dt);
+  return launch_fluxes<double, double>(ctx, qin, use_residual_dt);
 }
 
 static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CELL_THREADS - 1) / CELL_THREADS); }
+
+// nsteps S2O4 steps on a state of type S (q, qs, acc: the state, Q*, the
+// accumulator), R the reconstruction and flux type.
+template <class R, class S>
+static hgks_status step_loop(hgks_ctx ctx, S* q, S* qs, S* acc, int32_t nsteps, double dt_fixed) {
+  const Params& P = ctx->P;
+  for (int s = 0; s < nsteps; ++s) {
+    HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
+    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->sc, ctx->cfg.cfl, dt_fixed);
+    HIP_TRY(ctx, prof_end(ctx));
+    hgks_status r = launch_fluxes<R, S>(ctx, q, 0);
+    if (r != HGKS_OK) return r;
+    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
+    hipLaunchKernelGGL((update_kernel<1, S>), dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, q, qs, acc,
+                       ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
+    HIP_TRY(ctx, prof_end(ctx));
+    r = launch_fluxes<R, S>(ctx, qs, 0);
+    if (r != HGKS_OK) return r;
+    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
+    hipLaunchKernelGGL((update_kernel<2, S>), dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, q, qs, acc,
+                       ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
+    HIP_TRY(ctx, prof_end(ctx));
+    if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX) {
+      double vol = 1.0;
+      for (int a = 0; a < 3; ++a) vol *= ctx->cfg.hi[a] - ctx->cfg.lo[a];
+      HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
+      hipLaunchKernelGGL(mass_flux_kernel, dim3(1), dim3(256), 0, ctx->stream, ctx->mpart, (int)cell_blocks(P),
+                         1.0 / vol, ctx->mf, ctx->sc);
+      HIP_TRY(ctx, prof_end(ctx));
+    }
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  return HGKS_OK;
+}
+
 
 // ---- batched ensemble: host side ------------------------------------------
 
@@ -1403,6 +1453,7 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   ctx->part = reinterpret_cast<double*>(ctx->ws + L.part);
   ctx->qref = reinterpret_cast<double*>(ctx->ws + L.qref);
   ctx->mf = reinterpret_cast<double*>(ctx->ws + L.mf);
+  ctx->q32 = precision_fp32(*cfg) ? reinterpret_cast<float*>(ctx->ws + L.q32) : nullptr;
   ctx->mpart = reinterpret_cast<double*>(ctx->ws + L.mpart);
 
   // geometry: widths, d(index)/dx at faces, Gauss points and centres
@@ -1463,33 +1514,22 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
 hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
   if (!ctx || nsteps < 0 || !std::isfinite(dt_fixed) || !ctx->members.empty()) return HGKS_E_INVALID;
   if (ctx->latched != HGKS_OK) return ctx->latched;
-  const Params& P = ctx->P;
-  for (int s = 0; s < nsteps; ++s) {
-    HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
-    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->sc, ctx->cfg.cfl, dt_fixed);
-    HIP_TRY(ctx, prof_end(ctx));
-    hgks_status r = launch_fluxes_any(ctx, ctx->q, 0);
-    if (r != HGKS_OK) return r;
-    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
-    hipLaunchKernelGGL(update_kernel<1>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
-                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
-    HIP_TRY(ctx, prof_end(ctx));
-    r = launch_fluxes_any(ctx, ctx->qs, 0);
-    if (r != HGKS_OK) return r;
-    HIP_TRY(ctx, prof_begin(ctx, PROF_UPDATE));
-    hipLaunchKernelGGL(update_kernel<2>, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->qs,
-                       ctx->acc, ctx->F[0], ctx->F[1], ctx->F[2], P, ctx->sc, ctx->mpart);
-    HIP_TRY(ctx, prof_end(ctx));
-    if (P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX) {
-      double vol = 1.0;
-      for (int a = 0; a < 3; ++a) vol *= ctx->cfg.hi[a] - ctx->cfg.lo[a];
-      HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
-      hipLaunchKernelGGL(mass_flux_kernel, dim3(1), dim3(256), 0, ctx->stream, ctx->mpart, (int)cell_blocks(P),
-                         1.0 / vol, ctx->mf, ctx->sc);
-      HIP_TRY(ctx, prof_end(ctx));
-    }
-    HIP_TRY(ctx, hipGetLastError());
+  if (!precision_fp32(ctx->cfg)) {
+    if (precision_mixed(ctx->cfg)) return step_loop<float, double>(ctx, ctx->q, ctx->qs, ctx->acc, nsteps, dt_fixed);
+    return step_loop<double, double>(ctx, ctx->q, ctx->qs, ctx->acc, nsteps, dt_fixed);
   }
+  // FP32 path: the caller's FP64 state in (rounded on the first call, exact
+  // afterwards since it then holds FP32 values), the steps on the FP32 working
+  // copy, the result back to the caller's state.
+  const size_t n = 5 * cells(ctx->P);
+  const unsigned g = (unsigned)((n + CELL_THREADS - 1) / CELL_THREADS);
+  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->q32, n);
+  float* qs = reinterpret_cast<float*>(ctx->qs);
+  float* acc = reinterpret_cast<float*>(ctx->acc);
+  hgks_status r = step_loop<float, float>(ctx, ctx->q32, qs, acc, nsteps, dt_fixed);
+  if (r != HGKS_OK) return r;
+  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q32, ctx->q, n);
+  HIP_TRY(ctx, hipGetLastError());
   return HGKS_OK;
 }
 
@@ -1598,7 +1638,7 @@ hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t
   for (int i = 0; i < n; ++i) {
     if (validate(&cfgs[i], nullptr) != HGKS_OK) return HGKS_E_INVALID;
     if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
-    if (cfgs[i].flags != 0) return HGKS_E_UNSUPPORTED;
+    if (cfgs[i].flags != 0 || cfgs[i].precision == HGKS_FP32) return HGKS_E_UNSUPPORTED;
     total += align256(make_layout(cfgs[i]).total);
   }
   const std::vector<int> pre = batch_prefix(n, cfgs);

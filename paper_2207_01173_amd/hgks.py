@@ -19,7 +19,7 @@ ABI_VERSION = 2
 HGKS_FLAG_CONSTANT_MASS_FLUX = 1
 HGKS_OK, HGKS_E_INVALID, HGKS_E_NOMEM, HGKS_E_DEVICE, HGKS_E_NONFINITE, HGKS_E_NEGATIVE_STATE, HGKS_E_UNSUPPORTED = range(7)
 BC_PERIODIC, BC_ISOTHERMAL_WALL = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, FP32 = 0, 1, 2
 
 EXPORTED = [
     "hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",

@@ -179,3 +179,45 @@ def test_batch_rejects_mass_flux_flag(hg):
     with pytest.raises(hg.HGKSError) as e:
         hg.hgks_batch_workspace_size([cfg])
     assert e.value.status == hg.HGKS_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("ma", [0.1, 0.29])
+def test_fp32_error_is_small_and_stated(hg, oracle, ma):
+    """Whole-code FP32 path (state, stages and update in FP32) vs the FP64
+    oracle after 10 steps of the 32^3 TGV.  The state is rounded to FP32 twice
+    per step (unit roundoff 6e-8), on top of the FP32 reconstruction and flux
+    of the mixed path: bars 2e-6 on rho and rho E (relative max-norm), 2e-5 on
+    momentum against |m|max, 2e-6 on E_k, 1e-3 on eps_com."""
+    p = W.tgv_params(32, ma=ma, re=1600.0, pr=0.72, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    dt = oracle.cfl_dt(p, q0)
+    ref, _ = oracle.step(p, q0, 10, dt)
+    s = hg.Solver(p, q0, precision=hg.FP32)
+    s.step(10, dt)
+    got = s.state()
+    st = s.stats()
+    s.close()
+    err = rel_err(got, ref)
+    mscale = np.sqrt((ref[1:4] ** 2).sum(axis=0)).max()
+    merr = np.abs(got[1:4] - ref[1:4]).max(axis=(1, 2, 3)) / mscale
+    so = oracle.stats(p, ref)
+    eEk = abs(st["Ek"] - so["Ek"]) / so["Ek"]
+    eeps = abs(st["eps_com"] - so["eps_com"]) / so["eps_com"]
+    say(f"fp32 TGV32 Ma={ma}: state rel err per component {err}, momentum vs |m|max {merr}, "
+        f"E_k rel err {eEk:.2e}, eps_com rel err {eeps:.2e}")
+    assert np.isfinite(got).all()
+    assert err[0] <= 2e-6 and err[4] <= 2e-6 and (merr <= 2e-5).all(), (err, merr)
+    assert eEk <= 2e-6 and eeps <= 1e-3
+
+
+def test_fp32_uniform_flow_preserved(hg):
+    """A uniform state stays what its FP32 rounding is."""
+    n = (12, 10, 8)
+    p = W.tgv_params(n, ma=0.3, re=100.0)
+    nx, ny, nz = n
+    f = lambda v: np.full((nz, ny, nx), v)
+    q0 = np.ascontiguousarray(W.conserved(f(1.3), f(0.3), f(-0.2), f(0.1), f(2.0)))
+    s = hg.Solver(p, q0, precision=hg.FP32)
+    s.step(3, 0.01)
+    np.testing.assert_array_equal(s.state(), q0.astype(np.float32).astype(np.float64))
+    s.close()
