@@ -913,8 +913,9 @@ __global__ void begin_step_batch_kernel(BatchTable T) {
   sc->smax = 0ull;
 }
 
-// Reference state of the mixed path: the volume mean of Q, from the totals of
-// the statistics reduction.  Reconstruction works on deviations from it.
+// Reference state of the FP32-reconstruction paths (mixed, FP32): the volume
+// mean of Q, from the totals of the statistics reduction.  Reconstruction
+// works on deviations from it.
 __global__ void mean_state_kernel(const double* __restrict__ fin, double inv_vol, double* __restrict__ qref) {
   if (threadIdx.x < 5) qref[threadIdx.x] = fin[ST_TOT + threadIdx.x] * inv_vol;
 }
