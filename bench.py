@@ -355,7 +355,7 @@ def tgv_workload(n: int):
     return W.tgv_params(n, ma=0.29, re=1600.0, pr=0.72, cfl=0.5)
 
 
-def cpu_baseline(n_sample: int = 64, steps: int = 1) -> dict:
+def cpu_baseline(n_sample: int = 64, steps: int = 10) -> dict:
     """The oracle, as it stands, on the host cores: S2O4 steps of a TGV of the
     same physics at a smaller grid (the per-cell work does not depend on the
     grid size)."""
@@ -388,7 +388,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed and FP32 runs beside FP64")
-    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=64, help="grid of the oracle's timed sample")
+    ap.add_argument("--cpu-steps", type=int, default=10, help="S2O4 steps of the oracle's timed sample")
     ap.add_argument("--ensemble", action="store_true",
                     help="measure the 64-instance ensemble (batched vs per-instance loop) instead")
     ap.add_argument("--history", type=float, default=0.0, metavar="T_END",
@@ -522,7 +523,7 @@ def main() -> int:
             }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0
 
