@@ -45,9 +45,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "50f8e1241de166d5addb3b29d5c8ee3cd14399fa0171961f5889641b8df3337a",
-    "fetch_bytes": 1.0154e+10,
-    "write_bytes": 3.1605e+09,
+    "sources_sha256": "8b0546f1fa4efebb6d9935f79cc9444b3cf3b03e6c90ecd36f9fca36ae228fa6",
+    "fetch_bytes": 1.0193e+10,
+    "write_bytes": 3.0492e+09,
 }
 
 # MI355X published peaks
