@@ -221,3 +221,37 @@ def test_fp32_uniform_flow_preserved(hg):
     s.step(3, 0.01)
     np.testing.assert_array_equal(s.state(), q0.astype(np.float32).astype(np.float64))
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+@pytest.mark.parametrize("mass_flux", [False, True])
+def test_reduced_precision_channel(hg, oracle, precision, mass_flux):
+    """The mixed and FP32 paths on the walled, stretched channel (wall ghosts
+    recovered in FP64 from the state), with and without the mass-flux
+    controller: 5 CFL steps against the FP64 oracle.  Bars from the TGV cases:
+    2e-6 on rho and rho E, 2e-5 on momentum against |m|max.  The controller's
+    force is a difference of mean momenta over rho_b dt: with an FP64 state
+    (mixed) within 1e-4 relative; with the state stored in FP32 each step's
+    mean carries up to u32 max|rho U| of rounding (u32 = 2^-24), so after k
+    steps the force agrees to 3 k u32 max|rho U| / (rho_b dt)."""
+    p, q = channel_case((16, 24, 12))
+    p["mass_flux_control"] = mass_flux
+    prec = hg.MIXED if precision == "mixed" else hg.FP32
+    s = hg.Solver(p, q, precision=prec)
+    s.step(5, 0.0)
+    got = s.state()
+    st = s.stats()
+    s.close()
+    ref, dt_last, f_ref = oracle.step_force(p, q, 5, 0.0)
+    err = rel_err(got, ref)
+    mscale = np.sqrt((ref[1:4] ** 2).sum(axis=0)).max()
+    merr = np.abs(got[1:4] - ref[1:4]).max(axis=(1, 2, 3)) / mscale
+    say(f"{precision} channel mass_flux={mass_flux}: state err {err}, momentum vs |m|max {merr}, "
+        f"force {st['body_force_x']} vs {f_ref}")
+    assert np.isfinite(got).all()
+    assert err[0] <= 2e-6 and err[4] <= 2e-6 and (merr <= 2e-5).all(), (err, merr)
+    if precision == "mixed":
+        tol_f = 1e-4 * abs(f_ref)
+    else:
+        tol_f = 3 * 5 * 2.0 ** -24 * np.abs(q[1]).max() / (1.0 * 0.9 * dt_last)
+    assert abs(st["body_force_x"] - f_ref) <= tol_f, (st["body_force_x"], f_ref, tol_f)
