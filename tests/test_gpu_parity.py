@@ -267,3 +267,28 @@ def test_full_size_sampled_residual(hg, oracle):
     assert (eL <= tL).all() and (edL <= tdL).all()
     # and far below the size of the quantities themselves
     assert (eL / Lmax <= 1e-10).all() and (edL / dLmax <= 1e-8).all()
+
+
+@pytest.mark.parametrize("case", ["inviscid", "prandtl_one", "monatomic"])
+def test_degenerate_cases_parity(hg, oracle, case):
+    """Degenerate settings of the method, 5 steps of a smooth random periodic
+    flow on a ragged grid, FP64 path vs oracle to 1e-11: mu = 0 (tau = 0: the
+    time integrals take their tau -> 0 limits), Pr = 1 (no heat-flux
+    correction) and gamma = 5/3 (K = 0: no internal degrees of freedom)."""
+    n = (21, 18, 14)
+    kw = {"inviscid": {}, "prandtl_one": {"pr": 1.0}, "monatomic": {}}[case]
+    p = W.tgv_params(n, ma=0.3, re=400.0, **kw)
+    if case == "inviscid":
+        p["mu_ref"] = 0.0
+    if case == "monatomic":
+        p["gamma"] = 5.0 / 3.0
+    q = W.smooth_random(p, seed=11)
+    dt = 0.5 * oracle.cfl_dt(p, q)
+    s = hg.Solver(p, q)
+    s.step(5, dt)
+    got = s.state()
+    s.close()
+    ref, _ = oracle.step(p, q, 5, dt)
+    err = rel_err(got, ref)
+    say(f"degenerate {case}: state err {err}")
+    assert (err <= 1e-11).all(), err
