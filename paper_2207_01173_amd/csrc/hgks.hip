@@ -148,16 +148,23 @@ __device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params&
   }
 }
 
-template <int DIR> struct ReconTile;  // faces per tile in the local frame (n, t1, t2)
-template <> struct ReconTile<0> { static constexpr int TN = 16, T1 = 8, T2 = 1; };
-template <> struct ReconTile<1> { static constexpr int TN = 1, T1 = 8, T2 = 16; };
-template <> struct ReconTile<2> { static constexpr int TN = 1, T1 = 16, T2 = 8; };
+// Faces per reconstruction tile in the local frame (n, t1, t2).  x, the
+// contiguous axis, runs across lanes in every direction, W faces wide: 16 for
+// FP64 B (128-byte rows), 32 for FP32 B (also 128-byte rows).
+template <int DIR, int W> struct ReconTileW;
+template <int W> struct ReconTileW<0, W> { static constexpr int TN = W, T1 = 8, T2 = 1; };
+template <int W> struct ReconTileW<1, W> { static constexpr int TN = 1, T1 = 8, T2 = W; };
+template <int W> struct ReconTileW<2, W> { static constexpr int TN = 1, T1 = W, T2 = 8; };
+template <int DIR, class R> using ReconTile = ReconTileW<DIR, sizeof(R) == 8 ? 16 : 32>;
 
-template <int DIR> __host__ __device__ inline void recon_tile_extents(int S[3]) {
+template <int DIR, class R> __host__ __device__ inline void recon_tile_extents(int S[3]) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
-  S[DIR] = ReconTile<DIR>::TN;
-  S[D1] = ReconTile<DIR>::T1;
-  S[D2] = ReconTile<DIR>::T2;
+  S[DIR] = ReconTile<DIR, R>::TN;
+  S[D1] = ReconTile<DIR, R>::T1;
+  S[D2] = ReconTile<DIR, R>::T2;
+}
+template <int DIR, class R> constexpr int recon_tile_faces() {
+  return ReconTile<DIR, R>::TN * ReconTile<DIR, R>::T1 * ReconTile<DIR, R>::T2;
 }
 
 constexpr int RECON_THREADS = 256;
@@ -165,14 +172,14 @@ constexpr int RECON_THREADS = 256;
 // Normal sweep and first tangential sweep for a tile of faces of direction DIR.
 // LDS holds the 25 normal-sweep quantities of the tile plus a 2-face halo along
 // t1.  Output B[(q * 2 + g1) * NB + face] in the arithmetic type R.
-template <int DIR> constexpr int recon_lds_faces() {
-  return ReconTile<DIR>::TN * (ReconTile<DIR>::T1 + 4) * ReconTile<DIR>::T2;
+template <int DIR, class R> constexpr int recon_lds_faces() {
+  return ReconTile<DIR, R>::TN * (ReconTile<DIR, R>::T1 + 4) * ReconTile<DIR, R>::T2;
 }
 
 // Number of reconstruction tiles of direction DIR.
-template <int DIR> __host__ __device__ inline int recon_tiles(const Params& P) {
+template <int DIR, class R> __host__ __device__ inline int recon_tiles(const Params& P) {
   int S[3], be[3], bo[3];
-  recon_tile_extents<DIR>(S);
+  recon_tile_extents<DIR, R>(S);
   b_extents(P, DIR, be, bo);
   return ((be[0] + S[0] - 1) / S[0]) * ((be[1] + S[1] - 1) / S[1]) * ((be[2] + S[2] - 1) / S[2]);
 }
@@ -180,12 +187,13 @@ template <int DIR> __host__ __device__ inline int recon_tiles(const Params& P) {
 template <int DIR, class R, class ST = double>
 __device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Params& P,
                                            const double* __restrict__ qref, R* __restrict__ B, int lin,
-                                           R (*A)[recon_lds_faces<DIR>()]) {
+                                           R (*A)[recon_lds_faces<DIR, R>()]) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
-  constexpr int NA = recon_lds_faces<DIR>();
+  constexpr int NA = recon_lds_faces<DIR, R>();
+  constexpr int NF = recon_tile_faces<DIR, R>();  // 128 (FP64) or 256 (FP32)
 
   int S[3];
-  recon_tile_extents<DIR>(S);
+  recon_tile_extents<DIR, R>(S);
   int SA[3] = {S[0], S[1], S[2]};
   SA[D1] += 4;
   int be[3], bo[3];
@@ -246,60 +254,63 @@ __device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Param
   }
   __syncthreads();
 
-  // ---- first tangential sweep: both Gauss lines of one face per thread -----
-  // Waves 0-1 (h = 0) take the left-state quantities, waves 2-3 (h = 1) the
-  // right-state ones; the two Gauss lines share each stencil's candidates and
-  // WENO-Z factors.  The linear equilibrium slopes split 3 + 2 components.
-  const int o = threadIdx.x & 127, h = threadIdx.x >> 7;
-  int lo[3];
-  lo[0] = o % S[0];
-  lo[1] = (o / S[0]) % S[1];
-  lo[2] = o / (S[0] * S[1]);
-  int f[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) f[a] = org[a] + lo[a];
-  if (f[DIR] >= be[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) return;  // this thread only
-  int ai[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    int l[3] = {lo[0], lo[1], lo[2]};
-    l[D1] += j;  // A tile is offset by -2 along t1
-    ai[j] = (l[2] * SA[1] + l[1]) * SA[0] + l[0];
-  }
-  const int bp = face_pitch(be[0]);
-  const size_t NB = (size_t)bp * be[1] * be[2];
-  const size_t bidx = ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * bp + (f[0] - bo[0]);
-  HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
+  // ---- first tangential sweep: both Gauss lines of a face per work item ----
+  // Items (face, h): h = 0 the left-state quantities, h = 1 the right-state
+  // ones (whole waves share h); the two Gauss lines share each stencil's
+  // candidates and WENO-Z factors.  The linear equilibrium slopes split 3 + 2
+  // components.
+  const size_t NB = (size_t)face_pitch(be[0]) * be[1] * be[2];
   const size_t qstride = 2 * NB;
-  // B is written once and read once, by the flux kernel: non-temporal stores
-  // (no L2 allocation for a stream many times the cache's size).
-  auto put = [&](int q, const R val[2]) {
-    __builtin_nontemporal_store(val[0], &out[q * qstride]);
-    __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
-  };
-  auto stencil = [&](int row, R v[5]) {
+  for (int item = threadIdx.x; item < 2 * NF; item += RECON_THREADS) {
+    const int o = item % NF, h = item / NF;
+    int lo[3];
+    lo[0] = o % S[0];
+    lo[1] = (o / S[0]) % S[1];
+    lo[2] = o / (S[0] * S[1]);
+    int f[3];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = A[row][ai[j]];
-  };
-  const int qv = h ? B_QR : B_QL, qd = h ? B_DRT1 : B_DLT1, qn = h ? B_DRN : B_DLN;
-  const int av = h ? 5 : 0, an = h ? 15 : 10;
+    for (int a = 0; a < 3; ++a) f[a] = org[a] + lo[a];
+    if (f[DIR] >= be[DIR] || f[D1] >= P.n[D1] || f[D2] >= bo[D2] + be[D2]) continue;  // this item only
+    int ai[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    R v[5], val[2], der[2];
-    stencil(av + k, v);
-    gauss_value_slope2(v, val, der);
-    put(qv + k, val);
-    put(qd + k, der);
-    stencil(an + k, v);
-    gauss_value2(v, val);
-    put(qn + k, val);
-  }
-  const int k0 = h ? 3 : 0, k1 = h ? 5 : 3;
-  for (int k = k0; k < k1; ++k) {
-    R v[5], val[2];
-    stencil(20 + k, v);
-    gauss_linear2(v, val);
-    put(B_D0 + k, val);
+    for (int j = 0; j < 5; ++j) {
+      int l[3] = {lo[0], lo[1], lo[2]};
+      l[D1] += j;  // A tile is offset by -2 along t1
+      ai[j] = (l[2] * SA[1] + l[1]) * SA[0] + l[0];
+    }
+    const size_t bidx =
+        ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * face_pitch(be[0]) + (f[0] - bo[0]);
+    HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
+    // B is written once and read once, by the flux kernel: non-temporal stores
+    // (no L2 allocation for a stream many times the cache's size).
+    auto put = [&](int q, const R val[2]) {
+      __builtin_nontemporal_store(val[0], &out[q * qstride]);
+      __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
+    };
+    auto stencil = [&](int row, R v[5]) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) v[j] = A[row][ai[j]];
+    };
+    const int qv = h ? B_QR : B_QL, qd = h ? B_DRT1 : B_DLT1, qn = h ? B_DRN : B_DLN;
+    const int av = h ? 5 : 0, an = h ? 15 : 10;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R v[5], val[2], der[2];
+      stencil(av + k, v);
+      gauss_value_slope2(v, val, der);
+      put(qv + k, val);
+      put(qd + k, der);
+      stencil(an + k, v);
+      gauss_value2(v, val);
+      put(qn + k, val);
+    }
+    const int k0 = h ? 3 : 0, k1 = h ? 5 : 3;
+    for (int k = k0; k < k1; ++k) {
+      R v[5], val[2];
+      stencil(20 + k, v);
+      gauss_linear2(v, val);
+      put(B_D0 + k, val);
+    }
   }
 }
 
@@ -307,8 +318,8 @@ template <int DIR, class R, class ST>
 __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const ST* __restrict__ q, Params P,
                                                               const double* __restrict__ qref,
                                                               R* __restrict__ B) {
-  __shared__ R A[25][recon_lds_faces<DIR>()];
-  recon_tile<DIR, R, ST>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR>(P)), A);
+  __shared__ R A[25][recon_lds_faces<DIR, R>()];
+  recon_tile<DIR, R, ST>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR, R>(P)), A);
 }
 
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
@@ -874,7 +885,7 @@ __device__ __forceinline__ int find_instance(const BatchTable& T, int row, int t
 // blocks are XCD-remapped so each XCD's L2 holds neighbouring tiles.
 template <int DIR, class R>
 __global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T, int t0, int t1, int src_qs) {
-  __shared__ R A[25][recon_lds_faces<DIR>()];
+  __shared__ R A[25][recon_lds_faces<DIR, R>()];
   const int t = t0 + xcd_linear_block(gridDim.x);
   if (t >= t1) return;
   int local;
@@ -1153,7 +1164,7 @@ static hgks_status launch_fluxes(hgks_ctx ctx, const S* qin, int use_residual_dt
   R* B = static_cast<R*>(ctx->B);
   const double* qref = ctx->qref;
   auto recon_blocks = [&](int d) {
-    return (unsigned)(d == 0 ? recon_tiles<0>(P) : (d == 1 ? recon_tiles<1>(P) : recon_tiles<2>(P)));
+    return (unsigned)(d == 0 ? recon_tiles<0, R>(P) : (d == 1 ? recon_tiles<1, R>(P) : recon_tiles<2, R>(P)));
   };
   auto flux_blocks = [&](int d) { return (unsigned)flux_tiles<16>(P, d); };
 #define HGKS_DIRECTION(D)                                                                                    \
@@ -1226,9 +1237,10 @@ static std::vector<int> batch_prefix(int n, const hgks_config* cfgs) {
     Params P{};
     for (int a = 0; a < 3; ++a) { P.n[a] = cfgs[i].n[a]; P.bc[a] = cfgs[i].bc[a]; }
     long long items[PRE_ROWS];
-    items[PRE_RECON + 0] = recon_tiles<0>(P);
-    items[PRE_RECON + 1] = recon_tiles<1>(P);
-    items[PRE_RECON + 2] = recon_tiles<2>(P);
+    const bool f32 = cfgs[i].precision != HGKS_FP64;  // FP32 B: the wider reconstruction tiles
+    items[PRE_RECON + 0] = f32 ? recon_tiles<0, float>(P) : recon_tiles<0, double>(P);
+    items[PRE_RECON + 1] = f32 ? recon_tiles<1, float>(P) : recon_tiles<1, double>(P);
+    items[PRE_RECON + 2] = f32 ? recon_tiles<2, float>(P) : recon_tiles<2, double>(P);
     for (int d = 0; d < 3; ++d) {
       items[flux_row<16>(d)] = flux_tiles<16>(P, d);
       items[flux_row<32>(d)] = flux_tiles<32>(P, d);
