@@ -45,9 +45,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "8b0546f1fa4efebb6d9935f79cc9444b3cf3b03e6c90ecd36f9fca36ae228fa6",
-    "fetch_bytes": 1.0193e+10,
-    "write_bytes": 3.0492e+09,
+    "sources_sha256": "e712290e27ad516f342c03577c8701f2d32fde42e51e99b18850ca9c618e7534",
+    "fetch_bytes": 1.0187e+10,
+    "write_bytes": 3.0511e+09,
 }
 
 # MI355X published peaks

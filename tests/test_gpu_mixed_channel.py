@@ -255,3 +255,26 @@ def test_reduced_precision_channel(hg, oracle, precision, mass_flux):
     else:
         tol_f = 3 * 5 * 2.0 ** -24 * np.abs(q[1]).max() / (1.0 * 0.9 * dt_last)
     assert abs(st["body_force_x"] - f_ref) <= tol_f, (st["body_force_x"], f_ref, tol_f)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_reduced_precision_ragged_tiles(hg, oracle, precision):
+    """FP32 face data use reconstruction tiles 32 faces wide along x.  A
+    72 x 20 x 36 TGV gives two full tiles and a ragged one along x in every
+    direction (73 x faces for the x sweep), ragged tiles along y and z too,
+    against the FP64 oracle after 5 CFL steps, to the TGV bars of the
+    reduced-precision paths (1e-5 on rho and rho E, on momentum against |m|max)."""
+    p = W.tgv_params((72, 20, 36), ma=0.29, re=1600.0, pr=0.72, cfl=0.5)
+    q0 = W.tgv_initial(p)
+    dt = oracle.cfl_dt(p, q0)
+    ref, _ = oracle.step(p, q0, 5, dt)
+    s = hg.Solver(p, q0, precision=hg.MIXED if precision == "mixed" else hg.FP32)
+    s.step(5, dt)
+    got = s.state()
+    s.close()
+    err = rel_err(got, ref)
+    mscale = np.sqrt((ref[1:4] ** 2).sum(axis=0)).max()
+    merr = np.abs(got[1:4] - ref[1:4]).max(axis=(1, 2, 3)) / mscale
+    say(f"{precision} TGV 72x20x36: state err {err}, momentum vs |m|max {merr}")
+    assert np.isfinite(got).all()
+    assert err[0] <= 1e-5 and err[4] <= 1e-5 and (merr <= 1e-5).all(), (err, merr)
