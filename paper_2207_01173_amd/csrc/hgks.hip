@@ -151,6 +151,16 @@ __device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params&
 // Faces per reconstruction tile in the local frame (n, t1, t2).  x, the
 // contiguous axis, runs across lanes in every direction, W faces wide: 16 for
 // FP64 B (128-byte rows), 32 for FP32 B (also 128-byte rows).
+// Where Gauss line g (of the two along t1) of face i sits within one quantity's
+// 2 NB entries of B.  FP64 face data interleave the two lines, 2 i + g, so a
+// 16-face tile row is one 256-byte run (the reconstruction's stores are the
+// cost there: 2.7 vs 3.2 ms per launch at 256^3); FP32 face data keep them in
+// two planes, g NB + i, which the FP32 flux kernel reads faster (6.0 vs 6.35 ms).
+template <class R> constexpr bool B_INTERLEAVED = sizeof(R) == 8;
+template <class R> __host__ __device__ constexpr size_t b_pos(size_t i, int g, size_t NB) {
+  return B_INTERLEAVED<R> ? 2 * i + g : (size_t)g * NB + i;
+}
+
 template <int DIR, int W> struct ReconTileW;
 template <int W> struct ReconTileW<0, W> { static constexpr int TN = W, T1 = 8, T2 = 1; };
 template <int W> struct ReconTileW<1, W> { static constexpr int TN = 1, T1 = 8, T2 = W; };
@@ -171,7 +181,8 @@ constexpr int RECON_THREADS = 256;
 
 // Normal sweep and first tangential sweep for a tile of faces of direction DIR.
 // LDS holds the 25 normal-sweep quantities of the tile plus a 2-face halo along
-// t1.  Output B[(q * 2 + g1) * NB + face] in the arithmetic type R.
+// t1.  Output: quantity q of B at B[q * 2 NB + b_pos(face, g1)] in the
+// arithmetic type R.
 template <int DIR, class R> constexpr int recon_lds_faces() {
   return ReconTile<DIR, R>::TN * (ReconTile<DIR, R>::T1 + 4) * ReconTile<DIR, R>::T2;
 }
@@ -280,12 +291,18 @@ __device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Param
     }
     const size_t bidx =
         ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * face_pitch(be[0]) + (f[0] - bo[0]);
-    HGKS_GLOBAL R* out = gmem(B) + bidx;  // quantity q, Gauss line g at out[(2 q + g) NB]
     // B is written once and read once, by the flux kernel: non-temporal stores
     // (no L2 allocation for a stream many times the cache's size).
+    HGKS_GLOBAL R* out = gmem(B) + b_pos<R>(bidx, 0, NB);
+    using R2 = R __attribute__((ext_vector_type(2)));
     auto put = [&](int q, const R val[2]) {
-      __builtin_nontemporal_store(val[0], &out[q * qstride]);
-      __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
+      if constexpr (B_INTERLEAVED<R>) {
+        const R2 v2 = {val[0], val[1]};
+        __builtin_nontemporal_store(v2, reinterpret_cast<HGKS_GLOBAL R2*>(&out[q * qstride]));
+      } else {
+        __builtin_nontemporal_store(val[0], &out[q * qstride]);
+        __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
+      }
     };
     auto stencil = [&](int row, R v[5]) {
 #pragma unroll
@@ -386,7 +403,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
     bi[j] = (uint32_t)(sizeof(R) *
-                       ((size_t)g1 * NB + ((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * bp + (b[0] - bo[0])));
+                       b_pos<R>(((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * bp + (b[0] - bo[0]), g1, NB));
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
