@@ -45,9 +45,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "e712290e27ad516f342c03577c8701f2d32fde42e51e99b18850ca9c618e7534",
-    "fetch_bytes": 1.0187e+10,
-    "write_bytes": 3.0511e+09,
+    "sources_sha256": "e4e24d1be22018990396a48860e399657f0811400ea1d9b0ef5f3833b2c93dbb",
+    "fetch_bytes": 1.0006e+10,
+    "write_bytes": 3.3294e+09,
 }
 
 # MI355X published peaks
