@@ -9,6 +9,8 @@ kernel: second tangential sweep, Gauss-point BGK flux, face assembly) against
 the FP64 vector ALU peak, with its duration measured by HIP events on the
 library's stream over the timed region.  `cpu_baseline` times the oracle
 (plain FP64 CPU implementation) on a bounded sample of the same workload.
+`repeats` lists the FP64 path's ms/step over the timed block and further
+blocks of the same number of steps (their median and run-to-run spread).
 """
 from __future__ import annotations
 
@@ -16,6 +18,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -385,6 +388,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="blocks of --steps steps timed on the FP64 path (the first gives value; all give the spread)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed and FP32 runs beside FP64")
@@ -470,10 +475,25 @@ def main() -> int:
         }
         elapsed = t1 - t0
         state = solver.state()
+        spread = None
+        if prec == hgks.FP64 and args.repeats > 1:
+            # run-to-run spread: further blocks of K steps after the timed one
+            # (the solution keeps advancing; `value` is the first block)
+            per_step = [elapsed / args.steps * 1e3]
+            for r in range(args.repeats - 1):
+                torch.cuda.synchronize()
+                r0 = time.perf_counter()
+                solver.step(args.steps, 0.0)
+                torch.cuda.synchronize()
+                per_step.append((time.perf_counter() - r0) / args.steps * 1e3)
+                print(f"# {prec_name}: repeat {r + 2} of {args.repeats}: {per_step[-1]:.3f} ms/step",
+                      file=sys.stderr, flush=True)
+            spread = {"blocks": args.repeats, "ms_per_step": [round(x, 3) for x in per_step],
+                      "median_ms_per_step": round(float(statistics.median(per_step)), 3)}
         solver.close()
-        return elapsed, roofline, st, state
+        return elapsed, roofline, st, state, spread
 
-    elapsed, roofline, st, state64 = run("fp64")
+    elapsed, roofline, st, state64, spread = run("fp64")
     cell_stages = 2.0 * n ** 3 * args.steps
     value = cell_stages / elapsed
     out = {
@@ -499,11 +519,13 @@ def main() -> int:
         },
         "roofline": roofline,
     }
+    if spread:
+        out["repeats"] = spread
     if not args.no_mixed:
         dtypes = {"mixed": "f32 reconstruction and flux on deviations from the mean state, f64 state/update/reductions",
                   "fp32": "f32 state, stages and update, f32 reconstruction and flux, f64 face fluxes and reductions"}
         for name in ("mixed", "fp32"):
-            m_elapsed, m_roof, m_st, state_m = run(name)
+            m_elapsed, m_roof, m_st, state_m, _ = run(name)
             # stated error of the reduced-precision path against the FP64 path at matched steps
             rel = (abs(state_m - state64).max(axis=(1, 2, 3)) / abs(state64).max(axis=(1, 2, 3)))
             mom = abs(state_m[1:4] - state64[1:4]).max() / ((state64[1:4] ** 2).sum(axis=0) ** 0.5).max()

@@ -72,15 +72,15 @@ def tgv_initial(p):
     U = V0 sin x cos y cos z, V = -V0 cos x sin y cos z, W = 0,
     p = p0 + rho0 V0^2/16 (cos 2x + cos 2y)(cos 2z + 2), rho = p / T0."""
     nx, ny, nz = p["n"]
-    x = cell_centres(nx, p["lo"][0], p["hi"][0])
-    y = cell_centres(ny, p["lo"][1], p["hi"][1])
-    z = cell_centres(nz, p["lo"][2], p["hi"][2])
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    # separable factors on 1-D axes (broadcast to [z][y][x] by the products)
+    x = cell_centres(nx, p["lo"][0], p["hi"][0])[None, None, :]
+    y = cell_centres(ny, p["lo"][1], p["hi"][1])[None, :, None]
+    z = cell_centres(nz, p["lo"][2], p["hi"][2])[:, None, None]
     v0, rho0, p0 = p["v0"], p["rho0"], p["p0"]
-    U = v0 * np.sin(X) * np.cos(Y) * np.cos(Z)
-    V = -v0 * np.cos(X) * np.sin(Y) * np.cos(Z)
+    U = v0 * np.sin(x) * np.cos(y) * np.cos(z)
+    V = -v0 * np.cos(x) * np.sin(y) * np.cos(z)
     W = np.zeros_like(U)
-    pr = p0 + rho0 * v0 * v0 / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    pr = p0 + rho0 * v0 * v0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
     rho = pr / (p0 / rho0)
     return np.ascontiguousarray(conserved(rho, U, V, W, pr, p["gamma"]))
 

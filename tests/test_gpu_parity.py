@@ -237,19 +237,19 @@ def residual_tolerances(p, q, dt, K=1000.0):
     return K * eps * fscale / hmin, 12.0 * K * eps * fscale / (dt * hmin)
 
 
-def test_full_size_sampled_residual(hg, oracle):
-    """At the 256^3 benchmark workload (TGV, Ma 0.29), in the launch
-    configuration the benchmark uses: L and dL/dt at sampled cells (corners,
-    faces of the box, random interior) against the oracle's per-cell values,
-    within the rounding bounds of residual_tolerances."""
-    n = 256
+@pytest.mark.parametrize("n", [256, 512])
+def test_full_size_sampled_residual(hg, oracle, n):
+    """At the benchmark workloads (TGV 256^3 and 512^3, Ma 0.29), in the
+    launch configuration the benchmark uses: L and dL/dt at sampled cells
+    (corners, faces of the box, random interior) against the oracle's
+    per-cell values, within the rounding bounds of residual_tolerances."""
     p = W.tgv_params(n, ma=0.29, re=1600.0, pr=0.72)
     q = W.tgv_initial(p)
     dt = 0.5 * (2 * math.pi / n) / (1.0 + 1.0 / 0.29)
-    say("full-size residual 256^3 dt", dt)
+    say(f"full-size residual {n}^3 dt", dt)
     s = hg.Solver(p, q)
     L, dL = s.residual(s.q, dt)
-    rng = np.random.default_rng(256)
+    rng = np.random.default_rng(n)
     cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1), (n // 2, 0, n - 1)]
     cells += [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(60)]
     idx = np.array(cells)
