@@ -27,6 +27,18 @@ template <> __device__ __forceinline__ double pos_rcp<double>(double x) {
 // FP32 (mixed path): the hardware reciprocal, within 1 ulp.
 template <> __device__ __forceinline__ float pos_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reciprocal of a WENO-Z weight sum.  It scales every weight of a set by the
+// same factor, so its relative error e moves a reconstructed value v2 + s sum
+// w_k b_k only by e times the correction s sum w_k b_k, not by e times the
+// value: FP64 takes one Newton step on the hardware estimate (the estimate is
+// within 2^-24 of 1/x, the step within 2^-48), FP32 the hardware reciprocal.
+template <class R> __device__ __forceinline__ R wz_rcp(R x);
+template <> __device__ __forceinline__ double wz_rcp<double>(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+template <> __device__ __forceinline__ float wz_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // The three quadratic candidates through averages (v0,v1,v2), (v1,v2,v3),
 // (v2,v3,v4), written about the centre cell (x in [-1/2, 1/2]) as
 // p_k(x) = v2 - c_k/24 + b_k x + c_k x^2 / 2: c_k is the candidate's second
@@ -73,21 +85,20 @@ __device__ __forceinline__ void wz_factors(const R beta[3], R e[3]) {
   }
 }
 
-// Normalised weights alpha_k / sum alpha for the linear weights (d0, d1, d2).
+// Unnormalised weights a_k = d_k e_k for the linear weights (d0, d1, d2);
+// returns 1 / sum a.  A weighted candidate sum sum_k w_k x_k is formed as
+// (sum_k a_k x_k) / sum a: one multiply by the reciprocal instead of three.
 template <class R>
-__device__ __forceinline__ void wz_normalise(const R e[3], R d0, R d1, R d2, R w[3]) {
-  const R a0 = d0 * e[0], a1 = d1 * e[1], a2 = d2 * e[2];
-  const R inv = pos_rcp(a0 + a1 + a2);
-  w[0] = a0 * inv;
-  w[1] = a1 * inv;
-  w[2] = a2 * inv;
+__device__ __forceinline__ R wz_alpha(const R e[3], R d0, R d1, R d2, R a[3]) {
+  a[0] = d0 * e[0];
+  a[1] = d1 * e[1];
+  a[2] = d2 * e[2];
+  return wz_rcp(a[0] + a[1] + a[2]);
 }
 
-template <class R>
-__device__ __forceinline__ void wz_weights(const R beta[3], R d0, R d1, R d2, R w[3]) {
-  R e[3];
-  wz_factors(beta, e);
-  wz_normalise(e, d0, d1, d2, w);
+// sum_k a_k x_k
+template <class R> __device__ __forceinline__ R wz_dot(const R a[3], R x0, R x1, R x2) {
+  return a[0] * x0 + a[1] * x1 + a[2] * x2;
 }
 
 // Gauss points of the unit cell: s = -sqrt(3)/6 (g = 0) and +sqrt(3)/6 (g = 1).
@@ -123,20 +134,22 @@ template <class R> struct GaussPoint {
 template <class R>
 __device__ __forceinline__ R gauss_value(const R v[5], const GaussPoint<R>& gp) {
   const Candidates<R> k = candidates(v);
-  R w[3];
-  wz_weights(k.beta, gp.dv0, gp.dv1, gp.dv2, w);
-  return v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  R e[3], a[3];
+  wz_factors(k.beta, e);
+  const R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
+  return v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
 }
 
 // WENO-Z value and slope at a Gauss point (slope with the slope weights).
 template <class R>
 __device__ __forceinline__ void gauss_value_slope(const R v[5], const GaussPoint<R>& gp, R& val, R& der) {
   const Candidates<R> k = candidates(v);
-  R w[3];
-  wz_weights(k.beta, gp.dv0, gp.dv1, gp.dv2, w);
-  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_weights(k.beta, gp.dd0, gp.dd1, gp.dd2, w);
-  der = w[0] * (k.b[0] + k.c[0] * gp.s) + w[1] * (k.b[1] + k.c[1] * gp.s) + w[2] * (k.b[2] + k.c[2] * gp.s);
+  R e[3], a[3];
+  wz_factors(k.beta, e);
+  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
+  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, gp.dd0, gp.dd1, gp.dd2, a);
+  der = inv * wz_dot(a, k.b[0] + k.c[0] * gp.s, k.b[1] + k.c[1] * gp.s, k.b[2] + k.c[2] * gp.s);
 }
 
 // Both Gauss points of one stencil (index 0: s = -sqrt3/6, 1: s = +sqrt3/6)
@@ -145,32 +158,32 @@ __device__ __forceinline__ void gauss_value_slope(const R v[5], const GaussPoint
 template <class R>
 __device__ __forceinline__ void gauss_value2(const R v[5], R val[2]) {
   const Candidates<R> k = candidates(v);
-  R e[3], w[3];
+  R e[3], a[3];
   wz_factors(k.beta, e);
   const R s = R(GaussConst::s);
   const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
-  wz_normalise(e, d2, d1, d0, w);
-  val[0] = v[2] - s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, d0, d1, d2, w);
-  val[1] = v[2] + s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  R inv = wz_alpha(e, d2, d1, d0, a);
+  val[0] = v[2] - s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, d0, d1, d2, a);
+  val[1] = v[2] + s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
 }
 
 template <class R>
 __device__ __forceinline__ void gauss_value_slope2(const R v[5], R val[2], R der[2]) {
   const Candidates<R> k = candidates(v);
-  R e[3], w[3];
+  R e[3], a[3];
   wz_factors(k.beta, e);
   const R s = R(GaussConst::s);
   const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
   const R g0 = R(GaussConst::dd0), g1 = R(GaussConst::dd1), g2 = R(GaussConst::dd2);
-  wz_normalise(e, d2, d1, d0, w);
-  val[0] = v[2] - s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, g2, g1, g0, w);
-  der[0] = w[0] * (k.b[0] - k.c[0] * s) + w[1] * (k.b[1] - k.c[1] * s) + w[2] * (k.b[2] - k.c[2] * s);
-  wz_normalise(e, d0, d1, d2, w);
-  val[1] = v[2] + s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, g0, g1, g2, w);
-  der[1] = w[0] * (k.b[0] + k.c[0] * s) + w[1] * (k.b[1] + k.c[1] * s) + w[2] * (k.b[2] + k.c[2] * s);
+  R inv = wz_alpha(e, d2, d1, d0, a);
+  val[0] = v[2] - s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, g2, g1, g0, a);
+  der[0] = inv * wz_dot(a, k.b[0] - k.c[0] * s, k.b[1] - k.c[1] * s, k.b[2] - k.c[2] * s);
+  inv = wz_alpha(e, d0, d1, d2, a);
+  val[1] = v[2] + s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, g0, g1, g2, a);
+  der[1] = inv * wz_dot(a, k.b[0] + k.c[0] * s, k.b[1] + k.c[1] * s, k.b[2] + k.c[2] * s);
 }
 
 template <class R>
@@ -190,28 +203,28 @@ __device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
 template <class R>
 __device__ __forceinline__ void gauss_value_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& val_m) {
   const Candidates<R> k = candidates(v);
-  R e[3], w[3];
+  R e[3], a[3];
   wz_factors(k.beta, e);
-  wz_normalise(e, gp.dv0, gp.dv1, gp.dv2, w);
-  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, gp.dv2, gp.dv1, gp.dv0, w);
-  val_m = v[2] - gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
+  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
+  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, gp.dv2, gp.dv1, gp.dv0, a);
+  val_m = v[2] - gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
 }
 
 template <class R>
 __device__ __forceinline__ void gauss_value_slope_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& der,
                                                          R& val_m, R& der_m) {
   const Candidates<R> k = candidates(v);
-  R e[3], w[3];
+  R e[3], a[3];
   wz_factors(k.beta, e);
-  wz_normalise(e, gp.dv0, gp.dv1, gp.dv2, w);
-  val = v[2] + gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, gp.dd0, gp.dd1, gp.dd2, w);
-  der = w[0] * (k.b[0] + k.c[0] * gp.s) + w[1] * (k.b[1] + k.c[1] * gp.s) + w[2] * (k.b[2] + k.c[2] * gp.s);
-  wz_normalise(e, gp.dv2, gp.dv1, gp.dv0, w);
-  val_m = v[2] - gp.s * (w[0] * k.b[0] + w[1] * k.b[1] + w[2] * k.b[2]);
-  wz_normalise(e, gp.dd2, gp.dd1, gp.dd0, w);
-  der_m = w[0] * (k.b[0] - k.c[0] * gp.s) + w[1] * (k.b[1] - k.c[1] * gp.s) + w[2] * (k.b[2] - k.c[2] * gp.s);
+  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
+  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, gp.dd0, gp.dd1, gp.dd2, a);
+  der = inv * wz_dot(a, k.b[0] + k.c[0] * gp.s, k.b[1] + k.c[1] * gp.s, k.b[2] + k.c[2] * gp.s);
+  inv = wz_alpha(e, gp.dv2, gp.dv1, gp.dv0, a);
+  val_m = v[2] - gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  inv = wz_alpha(e, gp.dd2, gp.dd1, gp.dd0, a);
+  der_m = inv * wz_dot(a, k.b[0] - k.c[0] * gp.s, k.b[1] - k.c[1] * gp.s, k.b[2] - k.c[2] * gp.s);
 }
 
 // Linear (fifth-order) value at a Gauss point: the quartic through the averages.
@@ -228,12 +241,13 @@ __device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp)
 template <class R>
 __device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
   const Candidates<R> k = candidates(v);
-  R w[3];
-  wz_weights(k.beta, R(0.1), R(0.6), R(0.3), w);
+  R e[3], a[3];
+  wz_factors(k.beta, e);
+  const R inv = wz_alpha(e, R(0.1), R(0.6), R(0.3), a);
   const R twelfth = R(1.0 / 12.0);
-  val = v[2] + w[0] * (R(0.5) * k.b[0] + twelfth * k.c[0]) + w[1] * (R(0.5) * k.b[1] + twelfth * k.c[1]) +
-        w[2] * (R(0.5) * k.b[2] + twelfth * k.c[2]);
-  der = w[0] * (k.b[0] + R(0.5) * k.c[0]) + w[1] * (k.b[1] + R(0.5) * k.c[1]) + w[2] * (k.b[2] + R(0.5) * k.c[2]);
+  val = v[2] + inv * wz_dot(a, R(0.5) * k.b[0] + twelfth * k.c[0], R(0.5) * k.b[1] + twelfth * k.c[1],
+                            R(0.5) * k.b[2] + twelfth * k.c[2]);
+  der = inv * wz_dot(a, k.b[0] + R(0.5) * k.c[0], k.b[1] + R(0.5) * k.c[1], k.b[2] + R(0.5) * k.c[2]);
 }
 
 // Normal sweep at face i+1/2 from c[0..5] = Q_{i-2..i+3}: left/right values and
