@@ -37,6 +37,7 @@ struct Params {
   int bc[3];
   int flags;  // hgks_config.flags
   double gamma, gm1, K, mu_ref, T_ref, mu_exp, pr_fix, T_wall;
+  double iK3, iT_ref;  // 1/(K + 3); 1/T_ref (0 without a power law)
   double force[3];
   const double* hcell[3];  // cell widths
   const double* dface[3];  // d(index)/dx at faces 0..n
@@ -421,9 +422,9 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
   g.K3 = R(P.K + 3.0);
-  g.iK3 = R(1.0 / (P.K + 3.0));
+  g.iK3 = R(P.iK3);
   g.mu_ref = R(P.mu_ref);
-  g.iT_ref = R(P.T_ref > 0.0 ? 1.0 / P.T_ref : 0.0);
+  g.iT_ref = R(P.iT_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
   // Five stencil values of quantity qi along t2 (qi the same on every lane).
@@ -523,7 +524,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
   if (!valid || gpi != 0) return;  // this lane only
   const double area = gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
-  const double idt = 1.0 / dt, idt2 = 4.0 * idt * idt;
+  const double idt = pos_rcp(dt), idt2 = 4.0 * idt * idt;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -1475,6 +1476,8 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   P.mu_exp = cfg->mu_exp;
   P.pr_fix = 1.0 / cfg->prandtl - 1.0;
   P.T_wall = cfg->T_wall;
+  P.iK3 = 1.0 / (P.K + 3.0);
+  P.iT_ref = cfg->T_ref > 0.0 ? 1.0 / cfg->T_ref : 0.0;
   ctx->qs = reinterpret_cast<double*>(ctx->ws + L.qs);
   ctx->acc = reinterpret_cast<double*>(ctx->ws + L.acc);
   ctx->B = ctx->ws + L.B;

@@ -442,11 +442,11 @@ template <class R> struct GasParams {
   R pr_fix;    // 1/Pr - 1
 };
 
-// Integrals over [0, delta] of the six time factors of the BGK solution.
+// Integrals over [0, delta] of the six time factors of the BGK solution,
+// given eta = e^{-delta/tau} (tau > 0).
 template <class R>
-__device__ __forceinline__ void time_integrals(R tau, R itau, R delta, R C[6]) {
-  if (tau > R(0)) {
-    R eta = exp(-delta * itau);
+__device__ __forceinline__ void time_coefficients(R tau, R delta, R eta, R C[6]) {
+  {
     R om = R(1) - eta;
     R t2 = tau * tau;
     C[0] = delta - tau * om;
@@ -455,8 +455,22 @@ __device__ __forceinline__ void time_integrals(R tau, R itau, R delta, R C[6]) {
     C[3] = tau * om;
     C[4] = tau * delta * eta - R(2) * t2 * om;
     C[5] = -t2 * om;
+  }
+}
+
+// The time integrals over both windows, [0, dt] (C1) and [0, dt/2] (C2):
+// e^{-dt/tau} is the square of e^{-dt/(2 tau)}, so one exponential serves
+// both.  tau = 0 gives the limits C = (delta, 0, delta^2/2, 0, 0, 0).
+template <class R>
+__device__ __forceinline__ void time_integrals(R tau, R itau, R dt, R C1[6], R C2[6]) {
+  const R half = R(0.5) * dt;
+  if (tau > R(0)) {
+    const R eta2 = exp(-half * itau);
+    time_coefficients(tau, dt, eta2 * eta2, C1);
+    time_coefficients(tau, half, eta2, C2);
   } else {
-    C[0] = delta; C[1] = R(0); C[2] = R(0.5) * delta * delta; C[3] = R(0); C[4] = R(0); C[5] = R(0);
+    C1[0] = dt; C1[1] = R(0); C1[2] = R(0.5) * dt * dt; C1[3] = R(0); C1[4] = R(0); C1[5] = R(0);
+    C2[0] = half; C2[1] = R(0); C2[2] = R(0.5) * half * half; C2[3] = R(0); C2[4] = R(0); C2[5] = R(0);
   }
 }
 
@@ -509,8 +523,7 @@ __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const G
   if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 * g.iT_ref, g.mu_exp);
   const R tau = mu * pos_rcp(p0);
   const R itau = tau > R(0) ? pos_rcp(tau) : R(0);
-  time_integrals(tau, itau, dt, A.C1);
-  time_integrals(tau, itau, R(0.5) * dt, A.C2);
+  time_integrals(tau, itau, dt, A.C1, A.C2);
   A.hu2 = R(0.5) * (A.s0.U * A.s0.U + A.s0.V * A.s0.V + A.s0.W * A.s0.W);
 #pragma unroll
   for (int k = 0; k < 5; ++k) { A.F1[k] = R(0); A.F2[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
