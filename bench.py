@@ -48,9 +48,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "e4e24d1be22018990396a48860e399657f0811400ea1d9b0ef5f3833b2c93dbb",
-    "fetch_bytes": 1.0006e+10,
-    "write_bytes": 3.3294e+09,
+    "sources_sha256": "f4d25f01a5e12db9d22763577d966c80be03973a9650d16f741a13363b3b9305",
+    "fetch_bytes": 9.8160e+09,
+    "write_bytes": 2.4362e+09,
 }
 
 # MI355X published peaks
