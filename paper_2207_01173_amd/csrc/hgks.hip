@@ -27,10 +27,19 @@
 
 namespace hgks {
 
-// Quantities per face and Gauss line after the first tangential sweep.
-enum {
-  B_QL = 0, B_QR = 5, B_DLN = 10, B_DRN = 15, B_D0 = 20, B_DLT1 = 25, B_DRT1 = 30, B_COUNT = 35
-};
+// Quantities per face and Gauss line after the first tangential sweep, k the
+// conserved component.  The flux kernel's Gauss-point pairs read two
+// quantities together, and each such pair sits in adjacent planes:
+// (Q^l_k, Q^r_k), (dQ^l_k/dn, dQ^l_k/dt1), (dQ^r_k/dn, dQ^r_k/dt1); then the
+// equilibrium normal slopes dQ0_k/dn.
+constexpr int b_ql(int k) { return 2 * k; }
+constexpr int b_qr(int k) { return 2 * k + 1; }
+constexpr int b_dln(int k) { return 10 + 2 * k; }
+constexpr int b_dlt1(int k) { return 11 + 2 * k; }
+constexpr int b_drn(int k) { return 20 + 2 * k; }
+constexpr int b_drt1(int k) { return 21 + 2 * k; }
+constexpr int b_d0(int k) { return 30 + k; }
+constexpr int B_COUNT = 35;
 
 struct Params {
   int n[3];
@@ -160,6 +169,20 @@ __device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params&
 template <class R> constexpr bool B_INTERLEAVED = sizeof(R) == 8;
 template <class R> __host__ __device__ constexpr size_t b_pos(size_t i, int g, size_t NB) {
   return B_INTERLEAVED<R> ? 2 * i + g : (size_t)g * NB + i;
+}
+// Byte distance between a quantity of B and the next one (2 NB entries).
+template <class R> __host__ __device__ inline uint32_t second_pair_offset(size_t NB) {
+  return (uint32_t)(2 * NB * sizeof(R));
+}
+
+// The same pointer, declared uniform across the wave (it is: callers pass
+// block-uniform values), so that loads from it plus a 32-bit lane offset take
+// the scalar-base form instead of a 64-bit vector address per lane.
+__device__ __forceinline__ const HGKS_GLOBAL char* uniform_ptr(const HGKS_GLOBAL char* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const HGKS_GLOBAL char*>(((uint64_t)hi << 32) | lo);
 }
 
 template <int DIR, int W> struct ReconTileW;
@@ -309,25 +332,24 @@ __device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Param
 #pragma unroll
       for (int j = 0; j < 5; ++j) v[j] = A[row][ai[j]];
     };
-    const int qv = h ? B_QR : B_QL, qd = h ? B_DRT1 : B_DLT1, qn = h ? B_DRN : B_DLN;
     const int av = h ? 5 : 0, an = h ? 15 : 10;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       R v[5], val[2], der[2];
       stencil(av + k, v);
       gauss_value_slope2(v, val, der);
-      put(qv + k, val);
-      put(qd + k, der);
+      put(h ? b_qr(k) : b_ql(k), val);
+      put(h ? b_drt1(k) : b_dlt1(k), der);
       stencil(an + k, v);
       gauss_value2(v, val);
-      put(qn + k, val);
+      put(h ? b_drn(k) : b_dln(k), val);
     }
     const int k0 = h ? 3 : 0, k1 = h ? 5 : 3;
     for (int k = k0; k < k1; ++k) {
       R v[5], val[2];
       stencil(20 + k, v);
       gauss_linear2(v, val);
-      put(B_D0 + k, val);
+      put(b_d0(k), val);
     }
   }
 }
@@ -393,18 +415,28 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   const int bp = face_pitch(be[0]);
   const size_t NB = (size_t)bp * be[1] * be[2];
   const size_t qstride = 2 * NB;
-  // Lane byte offsets within one quantity's two Gauss lines (below 2^32:
-  // checked when the configuration is validated), added to a per-quantity base
-  // that is uniform across the block, so loads take the scalar-base form.
-  uint32_t bi[5];
+  // Addressing of B: every face of a block lies in one z plane of B for each
+  // stencil row j (z is the normal for y and z faces, and t2 for x faces,
+  // whose z then depends on j only), so a load is a block-uniform base (the
+  // quantity's start plus that plane's offset, held in scalar registers) plus
+  // a 32-bit lane offset within the plane: the position of the lane's face
+  // and Gauss line, and for the Gauss-point pairs the partner quantity's
+  // plane (one quantity further: the lane offsets stay below 2^32, checked
+  // when the configuration is validated).
+  const size_t plane = (size_t)bp * be[1];
+  const uint32_t pair_off = second_pair_offset<R>(NB);
+  const bool second = g2 != 0;
+  uint32_t off[5];     // lane offsets, pair partner included on the g2 = 1 lanes
+  size_t zoff[5];      // byte offsets of the stencil rows' z planes (block-uniform)
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     int b[3] = {f[0], f[1], f[2]};
     int t = f[D2] + j - 2;
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
-    bi[j] = (uint32_t)(sizeof(R) *
-                       b_pos<R>(((size_t)(b[2] - bo[2]) * be[1] + (b[1] - bo[1])) * bp + (b[0] - bo[0]), g1, NB));
+    zoff[j] = sizeof(R) * b_pos<R>((size_t)(b[2] - bo[2]) * plane, 0, NB);
+    const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
+    off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
@@ -427,23 +459,27 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.iT_ref = R(P.iT_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
+  // Block-uniform base of quantity qi and stencil row j.
+  auto row_base = [&](int qi, int j) {
+    return uniform_ptr(reinterpret_cast<const HGKS_GLOBAL char*>(Bg + (size_t)qi * qstride) + zoff[j]);
+  };
   // Five stencil values of quantity qi along t2 (qi the same on every lane).
   auto stencil = [&](int qi, R v[5]) {
-    const HGKS_GLOBAL char* base = reinterpret_cast<const HGKS_GLOBAL char*>(Bg + (size_t)qi * qstride);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(base + bi[j]);
+    for (int j = 0; j < 5; ++j) {
+      const uint32_t o = off[j] - (second ? pair_off : 0u);
+      v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(row_base(qi, j) + o);
+    }
   };
   // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
   // lane ^ 16) share every t2 stencil.  Each reconstructs one of two
   // quantities at both points (its own and the mirrored one) and swaps the
-  // mirrored result with its partner.  The g2 = 0 lane takes Q^l, the normal
-  // slopes; the g2 = 1 lane Q^r, the t1 slopes.
-  const bool second = g2 != 0;
-  auto stencil_pair = [&](int qi0, int dqi, R v[5]) {
-    const HGKS_GLOBAL char* base =
-        reinterpret_cast<const HGKS_GLOBAL char*>(Bg + ((size_t)qi0 + (second ? dqi : 0)) * qstride);
+  // mirrored result with its partner.  The g2 = 0 lane takes quantity qi0
+  // (Q^l, the normal slopes), the g2 = 1 lane the next one (Q^r, the t1
+  // slopes).
+  auto stencil_pair = [&](int qi0, R v[5]) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(base + bi[j]);
+    for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(row_base(qi0, j) + off[j]);
   };
   auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
 
@@ -456,7 +492,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     R v[5], val, der, val_m, der_m;
-    stencil_pair(B_QL + k, B_QR - B_QL, v);
+    stencil_pair(b_ql(k), v);
     gauss_value_slope_mirror(v, gp, val, der, val_m, der_m);
     const R ov = partner(val_m), od = partner(der_m);  // the other state at this lane's point
     ql[k] = R(double(second ? ov : val) + rl[k]);
@@ -472,7 +508,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      stencil_pair(B_DLN + k, B_DLT1 - B_DLN, pa[k]);
+      stencil_pair(b_dln(k), pa[k]);
       R val, val_m;
       gauss_value_mirror(pa[k], gp, val, val_m);
       const R o = partner(val_m);
@@ -488,7 +524,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      stencil_pair(B_DRN + k, B_DRT1 - B_DRN, pa[k]);
+      stencil_pair(b_drn(k), pa[k]);
       R val, val_m;
       gauss_value_mirror(pa[k], gp, val, val_m);
       const R o = partner(val_m);
@@ -505,7 +541,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     R dq0n[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      stencil(B_D0 + k, pa[k]);
+      stencil(b_d0(k), pa[k]);
       dq0n[k] = gauss_linear(pa[k], gp) * sn;
     }
     flux_finish(dq0n, g, acc, F1, F2);
@@ -1143,14 +1179,15 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
   }
   if ((size_t)c->n[0] * c->n[1] * c->n[2] > ((size_t)1 << 34)) return bad("grid too large");
   {
-    // the flux kernel addresses the two Gauss lines of one quantity of buffer B
-    // with 32-bit byte offsets
+    // the flux kernel's 32-bit lane offsets into buffer B span one quantity
+    // (both Gauss lines), the next quantity's offset and one z plane
     Params P{};
     for (int a = 0; a < 3; ++a) { P.n[a] = c->n[a]; P.bc[a] = c->bc[a]; }
     for (int d = 0; d < 3; ++d) {
       int be[3], bo[3];
       b_extents(P, d, be, bo);
-      if (2 * sizeof(double) * face_pitch(be[0]) * be[1] * be[2] >= ((size_t)1 << 32)) return bad("grid too large");
+      const size_t plane = (size_t)face_pitch(be[0]) * be[1];
+      if (2 * sizeof(double) * plane * ((size_t)be[2] + 1) >= ((size_t)1 << 32)) return bad("grid too large");
     }
   }
   if (!(c->gamma > 1.0 && c->gamma <= 5.0 / 3.0)) return bad("gamma out of (1, 5/3]");
