@@ -87,10 +87,11 @@ def test_status_strings():
 
 
 def test_largest_grids():
-    """The flux kernel addresses one quantity's two Gauss lines of buffer B with
-    32-bit byte offsets: 2 x 8 x pitch(n_x + 1) x n_y x n_z must stay below
-    2^32 (pitch = x extent rounded up to 32).  630^3 fits (640 x 630 x 630),
-    640^3 does not (672 x 640 x 640); 512^3 is well inside."""
+    """The flux kernel's 32-bit lane offsets into buffer B span one quantity
+    (both Gauss lines), the next quantity's offset and one z plane:
+    2 x 8 x pitch(n_x + 1) x n_y x (n_z + 1) must stay below 2^32 (pitch = x
+    extent rounded up to 32).  630^3 fits (640 x 630 x 631), 640^3 does not
+    (672 x 640 x 641); 512^3 is well inside."""
     for n, ok in ((512, True), (630, True), (640, False)):
         c = hgks.make_config(W.tgv_params(n))
         if ok:
