@@ -48,9 +48,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "f4d25f01a5e12db9d22763577d966c80be03973a9650d16f741a13363b3b9305",
-    "fetch_bytes": 9.8160e+09,
-    "write_bytes": 2.4362e+09,
+    "sources_sha256": "7827218bfc38079dcf829e3f9145d9e4fd0f4207863f5bc7681934b553168191",
+    "fetch_bytes": 9.7382e+09,
+    "write_bytes": 2.5683e+09,
 }
 
 # MI355X published peaks
