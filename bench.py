@@ -48,7 +48,7 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "7827218bfc38079dcf829e3f9145d9e4fd0f4207863f5bc7681934b553168191",
+    "sources_sha256": "4f0c6d91af5ec8327fa4e2a100972d0e9172923830956e7eff84972b1ba5ac91",
     "fetch_bytes": 9.7382e+09,
     "write_bytes": 2.5683e+09,
 }

@@ -130,31 +130,10 @@ template <class R> struct GaussPoint {
 // At a Gauss point (s^2 = 1/12) the candidate value is v2 + b_k s and its
 // slope b_k + c_k s.
 
-// WENO-Z value at a Gauss point.
-template <class R>
-__device__ __forceinline__ R gauss_value(const R v[5], const GaussPoint<R>& gp) {
-  const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  const R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
-  return v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-}
-
-// WENO-Z value and slope at a Gauss point (slope with the slope weights).
-template <class R>
-__device__ __forceinline__ void gauss_value_slope(const R v[5], const GaussPoint<R>& gp, R& val, R& der) {
-  const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
-  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, gp.dd0, gp.dd1, gp.dd2, a);
-  der = inv * wz_dot(a, k.b[0] + k.c[0] * gp.s, k.b[1] + k.c[1] * gp.s, k.b[2] + k.c[2] * gp.s);
-}
-
 // Both Gauss points of one stencil (index 0: s = -sqrt3/6, 1: s = +sqrt3/6)
-// from one set of candidates and WENO-Z factors; the same arithmetic as
-// gauss_value / gauss_value_slope at each point.
+// from one set of candidates and WENO-Z factors: at each point the value
+// v2 + s sum w_k b_k with the value weights of that point, and the slope
+// sum w_k (b_k + c_k s) with its slope weights.
 template <class R>
 __device__ __forceinline__ void gauss_value2(const R v[5], R val[2]) {
   const Candidates<R> k = candidates(v);
@@ -198,8 +177,8 @@ __device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
 }
 
 // WENO-Z at a lane's Gauss point (gp) and at the mirrored point -s (whose
-// linear weights are gp's reversed), from one set of candidates and factors.
-// At each point the arithmetic is that of gauss_value / gauss_value_slope.
+// linear weights are gp's reversed), from one set of candidates and factors;
+// at each point the same value and slope as gauss_value_slope2.
 template <class R>
 __device__ __forceinline__ void gauss_value_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& val_m) {
   const Candidates<R> k = candidates(v);
