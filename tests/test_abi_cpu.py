@@ -60,10 +60,12 @@ def test_workspace_size_and_validation():
         with pytest.raises(hgks.HGKSError) as e:
             hgks.hgks_workspace_size(c)
         assert e.value.status == hgks.HGKS_E_INVALID, field
-    c = hgks.make_config(p)
-    c.n[1] = 3
-    with pytest.raises(hgks.HGKSError):
-        hgks.hgks_workspace_size(c)
+    for n1 in (3, 0, -4):  # too few cells for the stencils, an empty or a negative extent
+        c = hgks.make_config(p)
+        c.n[1] = n1
+        with pytest.raises(hgks.HGKSError) as e:
+            hgks.hgks_workspace_size(c)
+        assert e.value.status == hgks.HGKS_E_INVALID
     c = hgks.make_config(p)
     c.bc[0] = hgks.BC_ISOTHERMAL_WALL  # walls only on y
     with pytest.raises(hgks.HGKSError):

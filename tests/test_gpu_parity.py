@@ -204,6 +204,37 @@ def test_nonfinite_state_latches(hg):
     s.close()
 
 
+def test_zero_and_negative_step_counts(hg):
+    """nsteps = 0 is a no-op (state bit for bit, time and step count
+    unchanged, also for the batched ensemble); nsteps < 0 is rejected before
+    any launch."""
+    p = W.tgv_params((12, 10, 8), ma=0.3, re=400.0)
+    q = W.tgv_initial(p)
+    s = hg.Solver(p, q)
+    s.step(2, 0.0)
+    before, st0 = s.state(), s.stats()
+    s.step(0, 0.0)
+    after, st1 = s.state(), s.stats()
+    np.testing.assert_array_equal(after, before)
+    assert (st1["t"], st1["steps"]) == (st0["t"], st0["steps"])
+    with pytest.raises(hg.HGKSError) as e:
+        s.step(-1, 0.0)
+    assert e.value.status == hg.HGKS_E_INVALID
+    np.testing.assert_array_equal(s.state(), before)
+    s.close()
+    b = hg.Batch([p, W.tgv_params(8)], [q, W.tgv_initial(W.tgv_params(8))])
+    b.step(1)
+    b.synchronize()
+    sb = b.stats(0)
+    b.step(0)
+    b.synchronize()
+    assert (b.stats(0)["t"], b.stats(0)["steps"]) == (sb["t"], sb["steps"])
+    with pytest.raises(hg.HGKSError) as e:
+        b.step(-1)
+    assert e.value.status == hg.HGKS_E_INVALID
+    b.close()
+
+
 def test_negative_pressure_latches(hg):
     p = W.tgv_params(16)
     q = W.tgv_initial(p)
