@@ -111,7 +111,13 @@ typedef struct {
   double body_force_x;   /* x body force in effect (the controller's with the mass-flux flag) */
 } hgks_stats_t;
 
-/* Workspace bytes for a configuration.  Errors: HGKS_E_INVALID. */
+/* Workspace bytes for a configuration.  Errors: HGKS_E_INVALID, also for a
+ * grid too large for the kernels' 32-bit offsets into the face buffer: for
+ * each face direction, with (e_x, e_y, e_z) that direction's face extents
+ * (n + 1 along the normal, n elsewhere, plus 2 ghost faces on each side of a
+ * wall axis when it is the second tangential one) and pitch = e_x rounded up
+ * to 32, 16 x pitch x e_y x (e_z + 1) bytes must stay below 2^32 (a 630^3
+ * grid is accepted, 640^3 is not). */
 hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes);
 
 /* Create a context over caller-owned memory: q_dev (state, in/out), ws_dev
