@@ -48,7 +48,7 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "4f0c6d91af5ec8327fa4e2a100972d0e9172923830956e7eff84972b1ba5ac91",
+    "sources_sha256": "7bd2ba5d9b27041ecb3beaba4e144121364aaf65dbd918d9999507cf77070cff",
     "fetch_bytes": 9.7382e+09,
     "write_bytes": 2.5683e+09,
 }

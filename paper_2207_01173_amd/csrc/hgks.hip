@@ -1412,7 +1412,7 @@ static hgks_status time_on_stream(hgks_ctx b, Fn fn, int reps, float* ms) {
 }
 
 static std::string tune_key(hgks_ctx b) {
-  std::string k = "hgks-batch-v2 prec=" + std::to_string(b->cfg.precision) + " n=" + std::to_string(b->members.size());
+  std::string k = "hgks-batch-v3 prec=" + std::to_string(b->cfg.precision) + " n=" + std::to_string(b->members.size());
   for (hgks_ctx m : b->members)
     k += " " + std::to_string(m->cfg.n[0]) + "x" + std::to_string(m->cfg.n[1]) + "x" + std::to_string(m->cfg.n[2]);
   return k;
