@@ -278,3 +278,52 @@ def test_reduced_precision_ragged_tiles(hg, oracle, precision):
     say(f"{precision} TGV 72x20x36: state err {err}, momentum vs |m|max {merr}")
     assert np.isfinite(got).all()
     assert err[0] <= 1e-5 and err[4] <= 1e-5 and (merr <= 1e-5).all(), (err, merr)
+
+
+def test_mixed_full_size_sampled_residual(hg, oracle):
+    """The reduced-precision flux at the benchmark workload (TGV 256^3, Ma
+    0.29), in the benchmark's launch configuration: L and dL/dt at sampled
+    cells against the FP64 oracle (hgks_residual takes an FP64 state, so this
+    covers the mixed and the whole-code FP32 contexts alike).  The Gauss-point
+    fluxes carry FP32 rounding, u32 = 2^-24 of the flux scale |F| (pressure
+    plus momentum and energy fluxes, as in the FP64 bound), so L = -sum dF/h
+    and dL/dt differ by K u32 |F| / h and 12 K u32 |F| / (dt h), K = 1000 the
+    FP64 bound's margin.  dL/dt is the 1/dt^2 cancellation 4 (I(dt) -
+    2 I(dt/2)) / dt^2 of the face integrals, I(dt) ~ dt |F|: the FP32 rounding
+    of I survives it as about 4 u32 |F| / dt per face, which here is several
+    per cent of max |dL/dt| (observed up to 17%), L is within 1e-3 of its
+    maximum.  In the S2O4 update dL/dt enters multiplied by dt^2 / 8: after
+    steps the state error stays near 1e-6 (the 32^3 oracle tests above, the
+    256^3 comparison with the FP64 path in the benchmark line)."""
+    import math
+
+    import torch
+
+    from test_gpu_parity import residual_tolerances
+
+    n = 256
+    p = W.tgv_params(n, ma=0.29, re=1600.0, pr=0.72)
+    q = W.tgv_initial(p)
+    dt = 0.5 * (2 * math.pi / n) / (1.0 + 1.0 / 0.29)
+    s = hg.Solver(p, q, precision=hg.MIXED)
+    L, dL = s.residual(s.q, dt)
+    rng = np.random.default_rng(2560)
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1), (n // 2, 0, n - 1)]
+    cells += [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(40)]
+    idx = np.array(cells)
+    Lg = L[:, idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy().T
+    dLg = dL[:, idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy().T
+    Lmax = L.abs().amax(dim=(1, 2, 3)).cpu().numpy()
+    dLmax = dL.abs().amax(dim=(1, 2, 3)).cpu().numpy()
+    s.close()
+    del L, dL
+    torch.cuda.empty_cache()
+    Lo, dLo = oracle.residual_at(p, q, dt, cells)
+    t64, td64 = residual_tolerances(p, q, dt)
+    scale = 2.0 ** -24 / np.finfo(np.float64).eps  # the FP64 bounds with u32 in place of u64
+    tL, tdL = t64 * scale, td64 * scale
+    eL, edL = np.abs(Lg - Lo).max(axis=0), np.abs(dLg - dLo).max(axis=0)
+    say("mixed 256^3 sampled abs L err", eL, "bound", tL, "rel to max", eL / Lmax)
+    say("mixed 256^3 sampled abs dL err", edL, "bound", tdL, "rel to max", edL / dLmax)
+    assert (eL <= tL).all() and (edL <= tdL).all()
+    assert (eL / Lmax <= 1e-3).all()
