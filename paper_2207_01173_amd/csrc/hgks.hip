@@ -536,7 +536,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
 
   // phase 4: equilibrium part and Prandtl correction
-  R F1[5], F2[5];
+  R Fn[5], Fd[5];  // F^n and dF^n/dt at this lane's Gauss point
   {
     R dq0n[5];
 #pragma unroll
@@ -544,30 +544,27 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
       stencil(b_d0(k), pa[k]);
       dq0n[k] = gauss_linear(pa[k], gp) * sn;
     }
-    flux_finish(dq0n, g, acc, F1, F2);
+    flux_finish(dq0n, g, acc, Fn, Fd);
   }
 
   // ---- 2x2 Gauss sum across the four lanes of the face -------------------
-  double s1[5], s2[5];
+  double sn5[5], sd5[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    s1[k] = double(F1[k]);
-    s2[k] = double(F2[k]);
-    s1[k] += __shfl_xor(s1[k], 16);
-    s2[k] += __shfl_xor(s2[k], 16);
-    s1[k] += __shfl_xor(s1[k], 32);
-    s2[k] += __shfl_xor(s2[k], 32);
+    sn5[k] = double(Fn[k]);
+    sd5[k] = double(Fd[k]);
+    sn5[k] += __shfl_xor(sn5[k], 16);
+    sd5[k] += __shfl_xor(sd5[k], 16);
+    sn5[k] += __shfl_xor(sn5[k], 32);
+    sd5[k] += __shfl_xor(sd5[k], 32);
   }
   if (!valid || gpi != 0) return;  // this lane only
-  const double area = gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
-  const double idt = pos_rcp(dt), idt2 = 4.0 * idt * idt;
+  const double qarea = 0.25 * gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    double I1 = 0.25 * area * s1[k];  // integral over [0, dt]
-    double I2 = 0.25 * area * s2[k];  // integral over [0, dt/2]
-    loc[k] = (4.0 * I2 - I1) * idt;
-    loc[5 + k] = (I1 - 2.0 * I2) * idt2;
+    loc[k] = qarea * sn5[k];
+    loc[5 + k] = qarea * sd5[k];
   }
   const int fpitch = face_pitch(fe[0]);
   const size_t NF = (size_t)fpitch * fe[1] * fe[2];

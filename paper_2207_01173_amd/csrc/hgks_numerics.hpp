@@ -421,36 +421,37 @@ template <class R> struct GasParams {
   R pr_fix;    // 1/Pr - 1
 };
 
-// Integrals over [0, delta] of the six time factors of the BGK solution,
-// given eta = e^{-delta/tau} (tau > 0).
+// Time coefficients of the two face quantities the update uses, the flux
+// F^n = (4 F(dt/2) - F(dt)) / dt and its derivative 4 (F(dt) - 2 F(dt/2)) / dt^2,
+// where F(delta) = sum_i C_i(delta) X_i with the six integrals over [0, delta]
+// of the BGK solution's time factors,
+//   C1 = delta - tau o, C2 = 2 tau^2 o - tau delta (1 + eta),
+//   C3 = delta^2/2 - tau delta + tau^2 o, C4 = tau o,
+//   C5 = tau delta eta - 2 tau^2 o, C6 = -tau^2 o  (eta = e^{-delta/tau}, o = 1 - eta).
+// Both windows share h = e^{-dt/(2 tau)} (e^{-dt/tau} = h^2), and the window
+// combinations N_i = 4 C_i(dt/2) - C_i(dt) and D_i = C_i(dt) - 2 C_i(dt/2)
+// reduce in closed form to products of o = 1 - h and g = 3 - h with no
+// difference of O(dt) terms left (combining the two windows' fluxes instead
+// would lose the rounding of dt |F| in a difference of order dt^2 |dF/dt|).
+// Cn = N / dt, Cd = 4 D / dt^2.  tau = 0 (h = 0) gives the Euler limits
+// Cn = (1, 0, 0, 0, 0, 0) and Cd = (0, 0, 1, 0, 0, 0) with no special case.
 template <class R>
-__device__ __forceinline__ void time_coefficients(R tau, R delta, R eta, R C[6]) {
-  {
-    R om = R(1) - eta;
-    R t2 = tau * tau;
-    C[0] = delta - tau * om;
-    C[1] = R(2) * t2 * om - tau * delta * (R(1) + eta);
-    C[2] = R(0.5) * delta * delta - tau * delta + t2 * om;
-    C[3] = tau * om;
-    C[4] = tau * delta * eta - R(2) * t2 * om;
-    C[5] = -t2 * om;
-  }
-}
-
-// The time integrals over both windows, [0, dt] (C1) and [0, dt/2] (C2):
-// e^{-dt/tau} is the square of e^{-dt/(2 tau)}, so one exponential serves
-// both.  tau = 0 gives the limits C = (delta, 0, delta^2/2, 0, 0, 0).
-template <class R>
-__device__ __forceinline__ void time_integrals(R tau, R itau, R dt, R C1[6], R C2[6]) {
-  const R half = R(0.5) * dt;
-  if (tau > R(0)) {
-    const R eta2 = exp(-half * itau);
-    time_coefficients(tau, dt, eta2 * eta2, C1);
-    time_coefficients(tau, half, eta2, C2);
-  } else {
-    C1[0] = dt; C1[1] = R(0); C1[2] = R(0.5) * dt * dt; C1[3] = R(0); C1[4] = R(0); C1[5] = R(0);
-    C2[0] = half; C2[1] = R(0); C2[2] = R(0.5) * half * half; C2[3] = R(0); C2[4] = R(0); C2[5] = R(0);
-  }
+__device__ __forceinline__ void time_integrals(R tau, R itau, R dt, R Cn[6], R Cd[6]) {
+  const R h = tau > R(0) ? exp(-(R(0.5) * dt) * itau) : R(0);
+  const R o = R(1) - h, t2 = tau * tau, og = o * (R(3) - h), o2 = o * o;
+  const R idt = pos_rcp(dt), i4dt2 = R(4) * idt * idt;
+  Cn[0] = (dt - tau * og) * idt;
+  Cn[1] = (R(2) * t2 * og - tau * dt * (R(1) + R(2) * h - h * h)) * idt;
+  Cn[2] = (t2 * og - tau * dt) * idt;
+  Cn[3] = tau * og * idt;
+  Cn[4] = (tau * dt * h * (R(2) - h) - R(2) * t2 * og) * idt;
+  Cn[5] = -t2 * og * idt;
+  Cd[0] = tau * o2 * i4dt2;
+  Cd[1] = tau * o * (dt * h - R(2) * tau * o) * i4dt2;
+  Cd[2] = (R(0.25) * dt * dt - t2 * o2) * i4dt2;
+  Cd[3] = -tau * o2 * i4dt2;
+  Cd[4] = tau * o * (R(2) * tau * o - dt * h) * i4dt2;
+  Cd[5] = t2 * o2 * i4dt2;
 }
 
 // Energy in the frame of U0 carried by a moment vector of psi:
@@ -466,10 +467,10 @@ __device__ __forceinline__ R thermal(const R v[5], R U, R V, R W, R hu2) {
 template <class R> struct FluxAcc {
   State<R> s0;          // interface equilibrium
   R ihl0, hu2;          // 1/(2 lambda0), |U0|^2 / 2
-  R C1[6], C2[6];       // time integrals over [0, dt] and [0, dt/2]
+  R Cn[6], Cd[6];       // time coefficients of F^n and of its time derivative
   R lm0, lm1, rm0, rm1; // half-space zeroth/first u-moments of the left/right states
-  R F1[5], F2[5];       // time-integrated flux, both windows
-  R w1, w2;             // thermal part of the conserved-variable integrals (Prandtl correction)
+  R Fn[5], Fd[5];       // F^n and dF^n/dt at the Gauss point (partial sums)
+  R wn, wd;             // thermal part of the conserved-variable integrals (Prandtl correction)
   R dq0t[2][5];         // tangential slopes of Q0 (exact derivative of the compatibility map)
 };
 
@@ -502,12 +503,12 @@ __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const G
   if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 * g.iT_ref, g.mu_exp);
   const R tau = mu * pos_rcp(p0);
   const R itau = tau > R(0) ? pos_rcp(tau) : R(0);
-  time_integrals(tau, itau, dt, A.C1, A.C2);
+  time_integrals(tau, itau, dt, A.Cn, A.Cd);
   A.hu2 = R(0.5) * (A.s0.U * A.s0.U + A.s0.V * A.s0.V + A.s0.W * A.s0.W);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) { A.F1[k] = R(0); A.F2[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
-  A.w1 = R(0);
-  A.w2 = R(0);
+  for (int k = 0; k < 5; ++k) { A.Fn[k] = R(0); A.Fd[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
+  A.wn = R(0);
+  A.wd = R(0);
 }
 
 // Phase 2/3: contributions of one non-equilibrium side (g_l with u > 0 when
@@ -554,8 +555,8 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
     assemble<R, 1, 3>(qa, Mh, X3);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      Acc.F1[k] += rho * (Acc.C1[3] * X1[k] + Acc.C1[4] * X2[k] + Acc.C1[5] * X3[k]);
-      Acc.F2[k] += rho * (Acc.C2[3] * X1[k] + Acc.C2[4] * X2[k] + Acc.C2[5] * X3[k]);
+      Acc.Fn[k] += rho * (Acc.Cn[3] * X1[k] + Acc.Cn[4] * X2[k] + Acc.Cn[5] * X3[k]);
+      Acc.Fd[k] += rho * (Acc.Cd[3] * X1[k] + Acc.Cd[4] * X2[k] + Acc.Cd[5] * X3[k]);
     }
   }
   {
@@ -566,8 +567,8 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
     const R y2 = thermal(Y, U0, V0, W0, Acc.hu2);
     assemble<R, 0, 3>(qa, Mh, Y);
     const R y3 = thermal(Y, U0, V0, W0, Acc.hu2);
-    Acc.w1 += rho * (Acc.C1[3] * y1 + Acc.C1[4] * y2 + Acc.C1[5] * y3);
-    Acc.w2 += rho * (Acc.C2[3] * y1 + Acc.C2[4] * y2 + Acc.C2[5] * y3);
+    Acc.wn += rho * (Acc.Cn[3] * y1 + Acc.Cn[4] * y2 + Acc.Cn[5] * y3);
+    Acc.wd += rho * (Acc.Cd[3] * y1 + Acc.Cd[4] * y2 + Acc.Cd[5] * y3);
   }
 #pragma unroll
   for (int d = 1; d < 3; ++d) {
@@ -584,8 +585,8 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
 // accumulated tangential ones, then the Prandtl correction of the energy
 // flux, q = thermal(F) - U0_n thermal(W).
 template <class R>
-__device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>& g, FluxAcc<R>& Acc, R F1[5],
-                                            R F2[5]) {
+__device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>& g, FluxAcc<R>& Acc, R Fn[5],
+                                            R Fd[5]) {
   const State<R>& s0 = Acc.s0;
   const R ihl0 = Acc.ihl0;
   VW<R> e;
@@ -627,8 +628,8 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
   assemble<R, 1, 3>(qa, Mf, X3);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    F1[k] = Acc.F1[k] + rho * (Acc.C1[0] * X1[k] + Acc.C1[1] * X2[k] + Acc.C1[2] * X3[k]);
-    F2[k] = Acc.F2[k] + rho * (Acc.C2[0] * X1[k] + Acc.C2[1] * X2[k] + Acc.C2[2] * X3[k]);
+    Fn[k] = Acc.Fn[k] + rho * (Acc.Cn[0] * X1[k] + Acc.Cn[1] * X2[k] + Acc.Cn[2] * X3[k]);
+    Fd[k] = Acc.Fd[k] + rho * (Acc.Cd[0] * X1[k] + Acc.Cd[1] * X2[k] + Acc.Cd[2] * X3[k]);
   }
   R Y[5];
   assemble<R, 0, 1>(unit, Mf, Y);
@@ -636,24 +637,26 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
   const R y2 = thermal(T, s0.U, s0.V, s0.W, Acc.hu2);
   assemble<R, 0, 3>(qa, Mf, Y);
   const R y3 = thermal(Y, s0.U, s0.V, s0.W, Acc.hu2);
-  const R w1 = Acc.w1 + rho * (Acc.C1[0] * y1 + Acc.C1[1] * y2 + Acc.C1[2] * y3);
-  const R w2 = Acc.w2 + rho * (Acc.C2[0] * y1 + Acc.C2[1] * y2 + Acc.C2[2] * y3);
-  const R qh1 = thermal(F1, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * w1;
-  const R qh2 = thermal(F2, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * w2;
-  F1[4] += g.pr_fix * qh1;
-  F2[4] += g.pr_fix * qh2;
+  const R wn = Acc.wn + rho * (Acc.Cn[0] * y1 + Acc.Cn[1] * y2 + Acc.Cn[2] * y3);
+  const R wd = Acc.wd + rho * (Acc.Cd[0] * y1 + Acc.Cd[1] * y2 + Acc.Cd[2] * y3);
+  // the heat flux is linear in the window, so the correction applies to F^n
+  // and to its derivative alike
+  const R qhn = thermal(Fn, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * wn;
+  const R qhd = thermal(Fd, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * wd;
+  Fn[4] += g.pr_fix * qhn;
+  Fd[4] += g.pr_fix * qhd;
 }
 
-// Time-integrated flux at one Gauss point, local frame (n, t1, t2), for the
-// windows [0, dt] (F1) and [0, dt/2] (F2).  Slopes in physical units.
+// F^n and dF^n/dt at one Gauss point, local frame (n, t1, t2).  Slopes in
+// physical units.
 template <class R>
 __device__ __forceinline__ void gp_flux(const R ql[5], const R qr[5], const R dql[3][5], const R dqr[3][5],
-                                        const R dq0n[5], const GasParams<R>& g, R dt, R F1[5], R F2[5]) {
+                                        const R dq0n[5], const GasParams<R>& g, R dt, R Fn[5], R Fd[5]) {
   FluxAcc<R> A;
   flux_begin(ql, qr, g, dt, A);
   flux_side<R, true>(ql, dql, g, A);
   flux_side<R, false>(qr, dqr, g, A);
-  flux_finish(dq0n, g, A, F1, F2);
+  flux_finish(dq0n, g, A, Fn, Fd);
 }
 
 }  // namespace hgks

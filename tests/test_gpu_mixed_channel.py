@@ -288,13 +288,11 @@ def test_mixed_full_size_sampled_residual(hg, oracle):
     fluxes carry FP32 rounding, u32 = 2^-24 of the flux scale |F| (pressure
     plus momentum and energy fluxes, as in the FP64 bound), so L = -sum dF/h
     and dL/dt differ by K u32 |F| / h and 12 K u32 |F| / (dt h), K = 1000 the
-    FP64 bound's margin.  dL/dt is the 1/dt^2 cancellation 4 (I(dt) -
-    2 I(dt/2)) / dt^2 of the face integrals, I(dt) ~ dt |F|: the FP32 rounding
-    of I survives it as about 4 u32 |F| / dt per face, which here is several
-    per cent of max |dL/dt| (observed up to 17%), L is within 1e-3 of its
-    maximum.  In the S2O4 update dL/dt enters multiplied by dt^2 / 8: after
-    steps the state error stays near 1e-6 (the 32^3 oracle tests above, the
-    256^3 comparison with the FP64 path in the benchmark line)."""
+    FP64 bound's margin.  dL/dt is built from closed-form time coefficients of
+    dF^n/dt (no difference of the two windows' integrals, whose FP32 rounding
+    of dt |F| would survive the 1/dt^2 cancellation as ~4 u32 |F| / dt per
+    face: 5-17% of max |dL/dt| when formed that way); observed L within 6e-4
+    and dL/dt within 7e-3 of their maxima, held here to 1e-3 and 2e-2."""
     import math
 
     import torch
@@ -326,4 +324,4 @@ def test_mixed_full_size_sampled_residual(hg, oracle):
     say("mixed 256^3 sampled abs L err", eL, "bound", tL, "rel to max", eL / Lmax)
     say("mixed 256^3 sampled abs dL err", edL, "bound", tdL, "rel to max", edL / dLmax)
     assert (eL <= tL).all() and (edL <= tdL).all()
-    assert (eL / Lmax <= 1e-3).all()
+    assert (eL / Lmax <= 1e-3).all() and (edL / dLmax <= 2e-2).all()
