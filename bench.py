@@ -48,9 +48,9 @@ FLOPS_RECON_PER_FACE = 6630.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "7bd2ba5d9b27041ecb3beaba4e144121364aaf65dbd918d9999507cf77070cff",
-    "fetch_bytes": 9.7382e+09,
-    "write_bytes": 2.5683e+09,
+    "sources_sha256": "2f3ae3d7d071855fbbc8642ded37be322764303c3b452513b7d5bba1ab0afe43",
+    "fetch_bytes": 9.7450e+09,
+    "write_bytes": 3.4718e+09,
 }
 
 # MI355X published peaks
