@@ -65,7 +65,7 @@ typedef enum {
   HGKS_E_DEVICE = 3,         /* HIP runtime error (see hgks_last_error) */
   HGKS_E_NONFINITE = 4,      /* the state holds NaN or Inf */
   HGKS_E_NEGATIVE_STATE = 5, /* density or pressure <= 0 somewhere */
-  HGKS_E_UNSUPPORTED = 6     /* valid request this build does not provide */
+  HGKS_E_UNSUPPORTED = 6     /* valid request the library does not provide */
 } hgks_status;
 
 enum { HGKS_BC_PERIODIC = 0, HGKS_BC_ISOTHERMAL_WALL = 1 }; /* wall: y axis only */
