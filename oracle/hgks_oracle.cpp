@@ -362,204 +362,6 @@ void gp_flux(const R ql[5], const R qr[5], const R dql[3][5], const R dqr[3][5],
 }
 
 /* ------------------------------------------------------------------------ */
-/* Economical evaluation of the same Gauss-point flux, for operation counts. */
-/* ------------------------------------------------------------------------ */
-/* Every moment <u^x G psi> of a polynomial G = sum_i u^i g_i(v, w, xi^2)
- * factorises into u-moments times (v, w, xi)-moments of the g_i, so the
- * (v, w, xi) part is computed once per Maxwellian and shared by the full- and
- * half-space u tables.  gp_flux_lean returns what gp_flux returns (up to
- * rounding); it exists to count the operations of this evaluation, which is
- * the one a GPU implementation performs.  r = v^2 + w^2 + xi^2.              */
-template <class R> struct TanMoments {
-  R v, w, r, vv, vw, ww, vr, wr, rr, vvv, vvw, vww, www, vvr, vwr, wwr, vrr, wrr;
-};
-
-template <class R> TanMoments<R> tangential_moments(const Moments<R>& m) {
-  TanMoments<R> t;
-  const R* V = m.v;
-  const R* W = m.w;
-  const R x1 = m.xi[1], x2 = m.xi[2];
-  t.v = V[1];
-  t.w = W[1];
-  t.r = V[2] + W[2] + x1;
-  t.vv = V[2];
-  t.vw = V[1] * W[1];
-  t.ww = W[2];
-  t.vr = V[3] + V[1] * W[2] + V[1] * x1;
-  t.wr = V[2] * W[1] + W[3] + W[1] * x1;
-  t.rr = V[4] + W[4] + x2 + 2.0 * (V[2] * W[2] + V[2] * x1 + W[2] * x1);
-  t.vvv = V[3];
-  t.vvw = V[2] * W[1];
-  t.vww = V[1] * W[2];
-  t.www = W[3];
-  t.vvr = V[4] + V[2] * W[2] + V[2] * x1;
-  t.vwr = V[3] * W[1] + V[1] * W[3] + V[1] * W[1] * x1;
-  t.wwr = V[2] * W[2] + W[4] + W[2] * x1;
-  t.vrr = V[5] + V[1] * W[4] + V[1] * x2 + 2.0 * (V[3] * W[2] + V[3] * x1 + V[1] * W[2] * x1);
-  t.wrr = V[4] * W[1] + W[5] + W[1] * x2 + 2.0 * (V[2] * W[3] + V[2] * W[1] * x1 + W[3] * x1);
-  return t;
-}
-
-/* (v, w, xi)-moments of one polynomial g: E[g], E[v g], E[w g], E[r g]. */
-template <class R> struct TanQuad { R e, v, w, r; };
-
-/* g = c0 + c1 v + c2 w + c3 r */
-template <class R> TanQuad<R> tq_affine(R c0, R c1, R c2, R c3, const TanMoments<R>& t) {
-  return {c0 + c1 * t.v + c2 * t.w + c3 * t.r, c0 * t.v + c1 * t.vv + c2 * t.vw + c3 * t.vr,
-          c0 * t.w + c1 * t.vw + c2 * t.ww + c3 * t.wr, c0 * t.r + c1 * t.vr + c2 * t.wr + c3 * t.rr};
-}
-/* g = v (c0 + c1 v + c2 w + c3 r) */
-template <class R> TanQuad<R> tq_v_affine(R c0, R c1, R c2, R c3, const TanMoments<R>& t) {
-  return {c0 * t.v + c1 * t.vv + c2 * t.vw + c3 * t.vr, c0 * t.vv + c1 * t.vvv + c2 * t.vvw + c3 * t.vvr,
-          c0 * t.vw + c1 * t.vvw + c2 * t.vww + c3 * t.vwr, c0 * t.vr + c1 * t.vvr + c2 * t.vwr + c3 * t.vrr};
-}
-/* g = w (c0 + c1 v + c2 w + c3 r) */
-template <class R> TanQuad<R> tq_w_affine(R c0, R c1, R c2, R c3, const TanMoments<R>& t) {
-  return {c0 * t.w + c1 * t.vw + c2 * t.ww + c3 * t.wr, c0 * t.vw + c1 * t.vvw + c2 * t.vww + c3 * t.vwr,
-          c0 * t.ww + c1 * t.vww + c2 * t.www + c3 * t.wwr, c0 * t.wr + c1 * t.vwr + c2 * t.wwr + c3 * t.wrr};
-}
-template <class R> TanQuad<R> tq_sum(const TanQuad<R>& a, const TanQuad<R>& b) {
-  return {a.e + b.e, a.v + b.v, a.w + b.w, a.r + b.r};
-}
-
-/* <u^x G psi> from the quads of g_0..g_{n-1} and a u-table mu[]:
- * (sum mu[x+i] g_i.e, sum mu[x+i+1] g_i.e, sum mu[x+i] g_i.v, sum mu[x+i] g_i.w,
- *  (sum mu[x+i+2] g_i.e + mu[x+i] g_i.r) / 2).                               */
-template <class R> void u_series_moment(const TanQuad<R>* g, int n, const R* mu, int x, R out[5]) {
-  R o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0, o4 = 0.0;
-  for (int i = 0; i < n; ++i) {
-    o0 += mu[x + i] * g[i].e;
-    o1 += mu[x + i + 1] * g[i].e;
-    o2 += mu[x + i] * g[i].v;
-    o3 += mu[x + i] * g[i].w;
-    o4 += mu[x + i + 2] * g[i].e + mu[x + i] * g[i].r;
-  }
-  out[0] = o0; out[1] = o1; out[2] = o2; out[3] = o3; out[4] = 0.5 * o4;
-}
-
-/* u-series of a . psi = (a0 + a2 v + a3 w + h r) + a1 u + h u^2, h = a4/2. */
-template <class R> void series_of(const R a[5], const TanMoments<R>& t, TanQuad<R> g[3]) {
-  R h = 0.5 * a[4];
-  g[0] = tq_affine(a[0], a[2], a[3], h, t);
-  g[1] = tq_affine(a[1], R(0.0), R(0.0), R(0.0), t);
-  g[2] = tq_affine(h, R(0.0), R(0.0), R(0.0), t);
-}
-/* u-series of u (a_n . psi) + v (a_t1 . psi) + w (a_t2 . psi). */
-template <class R> void series_transport(const R a[3][5], const TanMoments<R>& t, TanQuad<R> g[4]) {
-  R hn = 0.5 * a[0][4], h1 = 0.5 * a[1][4], h2 = 0.5 * a[2][4];
-  g[0] = tq_sum(tq_v_affine(a[1][0], a[1][2], a[1][3], h1, t), tq_w_affine(a[2][0], a[2][2], a[2][3], h2, t));
-  g[1] = tq_affine(a[0][0], a[0][2] + a[1][1], a[0][3] + a[2][1], hn, t);
-  g[2] = tq_affine(a[0][1], h1, h2, R(0.0), t);
-  g[3] = tq_affine(hn, R(0.0), R(0.0), R(0.0), t);
-}
-
-template <class R> R thermal_part(const R v[5], const State<R>& s0) {
-  R U2 = s0.U * s0.U + s0.V * s0.V + s0.W * s0.W;
-  return v[4] - (s0.U * v[1] + s0.V * v[2] + s0.W * v[3]) + 0.5 * U2 * v[0];
-}
-
-template <class R>
-void gp_flux_lean(const R ql[5], const R qr[5], const R dql[3][5], const R dqr[3][5], const R dq0n[5],
-                  const Gas<R>& g, R dt1, R dt2, R F1[5], R F2[5]) {
-  const R K = g.K;
-  State<R> sd[2] = {primitive(ql, g.gamma), primitive(qr, g.gamma)};
-  Moments<R> half[2];
-  maxwell_moments(sd[0], K, +1, half[0]);
-  maxwell_moments(sd[1], K, -1, half[1]);
-  R q0[5];
-  {
-    R hl[5], hr[5];
-    mom_psi(half[0], 0, 0, 0, 0, hl);
-    mom_psi(half[1], 0, 0, 0, 0, hr);
-    for (int k = 0; k < 5; ++k) q0[k] = sd[0].rho * hl[k] + sd[1].rho * hr[k];
-  }
-  State<R> s0 = primitive(q0, g.gamma);
-  R tau = collision_time(s0, g);
-  R C[2][6];
-  time_coefficients(tau, dt1, C[0]);
-  time_coefficients(tau, dt2, C[1]);
-  R Fs[2][5], Ws[2];
-  for (int w = 0; w < 2; ++w) {
-    for (int k = 0; k < 5; ++k) Fs[w][k] = 0.0;
-    Ws[w] = 0.0;
-  }
-  R dq0[3][5];
-  for (int k = 0; k < 5; ++k) { dq0[0][k] = dq0n[k]; dq0[1][k] = 0.0; dq0[2][k] = 0.0; }
-  for (int side = 0; side < 2; ++side) {
-    const State<R>& s = sd[side];
-    const R(*dq)[5] = side == 0 ? dql : dqr;
-    Moments<R> full;
-    maxwell_moments(s, K, 0, full);
-    TanMoments<R> t = tangential_moments(full);
-    R a[3][5], A[5], b[5];
-    for (int d = 0; d < 3; ++d) {
-      for (int k = 0; k < 5; ++k) b[k] = dq[d][k] / s.rho;
-      slope_solve(s, K, b, a[d]);
-    }
-    TanQuad<R> gt[4], ga[3];
-    series_transport(a, t, gt);
-    u_series_moment(gt, 4, full.u, 0, b);
-    for (int k = 0; k < 5; ++k) b[k] = -b[k];
-    slope_solve(s, K, b, A);
-    series_of(A, t, ga);
-    TanQuad<R> one = tq_affine(R(1.0), R(0.0), R(0.0), R(0.0), t);
-    R X1[5], X2[5], X3[5], Y1[5], Y2[5], Y3[5];
-    u_series_moment(&one, 1, half[side].u, 1, X1);
-    u_series_moment(gt, 4, half[side].u, 1, X2);
-    u_series_moment(ga, 3, half[side].u, 1, X3);
-    u_series_moment(&one, 1, half[side].u, 0, Y1);
-    u_series_moment(gt, 4, half[side].u, 0, Y2);
-    u_series_moment(ga, 3, half[side].u, 0, Y3);
-    R y1 = thermal_part(Y1, s0), y2 = thermal_part(Y2, s0), y3 = thermal_part(Y3, s0);
-    for (int w = 0; w < 2; ++w) {
-      for (int k = 0; k < 5; ++k) Fs[w][k] += s.rho * (C[w][3] * X1[k] + C[w][4] * X2[k] + C[w][5] * X3[k]);
-      Ws[w] += s.rho * (C[w][3] * y1 + C[w][4] * y2 + C[w][5] * y3);
-    }
-    for (int d = 1; d < 3; ++d) {
-      TanQuad<R> gd[3];
-      series_of(a[d], t, gd);
-      R tv[5];
-      u_series_moment(gd, 3, half[side].u, 0, tv);
-      for (int k = 0; k < 5; ++k) dq0[d][k] += s.rho * tv[k];
-    }
-  }
-  {
-    Moments<R> m0;
-    maxwell_moments(s0, K, 0, m0);
-    TanMoments<R> t = tangential_moments(m0);
-    R a[3][5], A[5], b[5], T[5];
-    for (int d = 0; d < 3; ++d) {
-      for (int k = 0; k < 5; ++k) b[k] = dq0[d][k] / s0.rho;
-      slope_solve(s0, K, b, a[d]);
-    }
-    TanQuad<R> gt[4], ga[3];
-    series_transport(a, t, gt);
-    u_series_moment(gt, 4, m0.u, 0, T);
-    for (int k = 0; k < 5; ++k) b[k] = -T[k];
-    slope_solve(s0, K, b, A);
-    series_of(A, t, ga);
-    TanQuad<R> one = tq_affine(R(1.0), R(0.0), R(0.0), R(0.0), t);
-    R X1[5], X2[5], X3[5], Y1[5], Y3[5];
-    u_series_moment(&one, 1, m0.u, 1, X1);
-    u_series_moment(gt, 4, m0.u, 1, X2);
-    u_series_moment(ga, 3, m0.u, 1, X3);
-    u_series_moment(&one, 1, m0.u, 0, Y1);
-    u_series_moment(ga, 3, m0.u, 0, Y3);
-    R y1 = thermal_part(Y1, s0), y2 = thermal_part(T, s0), y3 = thermal_part(Y3, s0);
-    for (int w = 0; w < 2; ++w) {
-      for (int k = 0; k < 5; ++k) Fs[w][k] += s0.rho * (C[w][0] * X1[k] + C[w][1] * X2[k] + C[w][2] * X3[k]);
-      Ws[w] += s0.rho * (C[w][0] * y1 + C[w][1] * y2 + C[w][2] * y3);
-    }
-  }
-  for (int w = 0; w < 2; ++w) {
-    R* F = w == 0 ? F1 : F2;
-    R q = thermal_part(Fs[w], s0) - s0.U * Ws[w];
-    for (int k = 0; k < 5; ++k) F[k] = Fs[w][k];
-    F[4] = F[4] + (1.0 / g.Pr - 1.0) * q;
-  }
-}
-
-/* ------------------------------------------------------------------------ */
 /* Fifth-order WENO-Z reconstruction (Sec. 2 last paragraph; R1-R5, R8)      */
 /* ------------------------------------------------------------------------ */
 /* Five consecutive cell averages v[0..4] centred at cells -2..2 (unit cell
@@ -1137,23 +939,34 @@ static double cfl_dt(const Grid& g, const double* q) {
 
 /* One S2O4 step (Eq. (two-stage)); both stages use the windows [0, dt] and
  * [0, dt/2] measured from the start of the stage (R10).                     */
+/* Stage 1 from Q^n, L(Q^n), dL/dt(Q^n): the intermediate state
+ * Q* = Q^n + dt/2 L + dt^2/8 dL/dt and the part of Q^{n+1} known after it,
+ * Q^n + dt L + dt^2/6 dL/dt.                                                */
+static inline void s2o4_stage1(double qn, double L, double dL, double dt, double& qs, double& acc) {
+  qs = qn + 0.5 * dt * L + 0.125 * dt * dt * dL;
+  acc = qn + dt * L + dt * dt / 6.0 * dL;
+}
+/* Stage 2: Q^{n+1} = (Q^n + dt L + dt^2/6 dL/dt) + dt^2/3 dL/dt(Q*).          */
+static inline double s2o4_stage2(double acc, double dLs, double dt) { return acc + dt * dt / 3.0 * dLs; }
+
 static void s2o4_step(const Grid& g, double* q, double dt) {
   size_t N = (size_t)g.n[0] * g.n[1] * g.n[2] * 5;
   std::vector<double> L(N), dL(N), qs(N), acc(N);
   residual(g, q, dt, L.data(), dL.data());
-  for (size_t m = 0; m < N; ++m) {
-    qs[m] = q[m] + 0.5 * dt * L[m] + 0.125 * dt * dt * dL[m];
-    acc[m] = q[m] + dt * L[m] + dt * dt / 6.0 * dL[m];
-  }
+  for (size_t m = 0; m < N; ++m) s2o4_stage1(q[m], L[m], dL[m], dt, qs[m], acc[m]);
   residual(g, qs.data(), dt, L.data(), dL.data());
-  for (size_t m = 0; m < N; ++m) q[m] = acc[m] + dt * dt / 3.0 * dL[m];
+  for (size_t m = 0; m < N; ++m) q[m] = s2o4_stage2(acc[m], dL[m], dt);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Statistics (Sec. 4.1): E_k and the total viscous dissipation              */
 /* ------------------------------------------------------------------------ */
 /* Velocity gradients: fourth-order central differences of U = m/rho at cell
- * centres on uniform periodic axes (R20).                                    */
+ * centres (R20), taken in index space and scaled by d(index)/dx at the cell
+ * centre, which on a uniform axis is 1/h and on the tanh-stretched y axis
+ * the inverse of the map's derivative.  Neighbours beyond a periodic axis
+ * wrap; beyond an isothermal no-slip wall they are the wall ghosts of R17,
+ * whose velocity is the mirrored interior cell's, reversed.                  */
 struct Stats {
   double Ek, eps_sol, eps_dil, eps_com;
   double total[5], max_abs[5], min_p, min_rho;
@@ -1188,16 +1001,31 @@ static void stats(const Grid& g, const double* q, double rho0, Stats& s) {
         minp = std::min(minp, p);
         minr = std::min(minr, v[0]);
       }
+  std::vector<double> dcen[3];  // d(index)/dx at the cell centres
+  for (int a = 0; a < 3; ++a) {
+    dcen[a].resize(g.n[a]);
+    for (int i = 0; i < g.n[a]; ++i) dcen[a][i] = 1.0 / dcoord(g.c, a, i + 0.5);
+  }
   auto D = [&](int comp, int axis, int i, int j, int k) {
     auto at = [&](int o) {
       int ii = i, jj = j, kk = k;
       int* t = axis == 0 ? &ii : (axis == 1 ? &jj : &kk);
-      int n = g.n[axis];
-      *t = ((*t + o) % n + n) % n;
-      return u[comp * N + ((size_t)kk * ny + jj) * nx + ii];
+      const int n = g.n[axis];
+      int m = *t + o;
+      double sign = 1.0;
+      if (m < 0 || m >= n) {
+        if (g.c.bc[axis] == 1) {
+          m = m < 0 ? -m - 1 : 2 * n - 1 - m;
+          sign = -1.0;
+        } else {
+          m = (m % n + n) % n;
+        }
+      }
+      *t = m;
+      return sign * u[comp * N + ((size_t)kk * ny + jj) * nx + ii];
     };
-    double h = g.h[axis][0];
-    return (at(-2) - 8.0 * at(-1) + 8.0 * at(1) - at(2)) / (12.0 * h);
+    const int ia = axis == 0 ? i : (axis == 1 ? j : k);
+    return (at(-2) - 8.0 * at(-1) + 8.0 * at(1) - at(2)) / 12.0 * dcen[axis][ia];
   };
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -1319,22 +1147,6 @@ void hgo_gp_flux(const double ql[5], const double qr[5], const double d[30], con
   gp_flux(ql, qr, dql, dqr, dq0n, g, dt1, dt2, F1, F2);
 }
 
-/* The economical evaluation of the same flux (operation counts). */
-void hgo_gp_flux_lean(const double ql[5], const double qr[5], const double d[30], const double dq0n[5],
-                      const double gas[6], double dt1, double dt2, double F1[5], double F2[5]) {
-  Gas<double> g;
-  g.gamma = gas[0];
-  g.K = (5.0 - 3.0 * gas[0]) / (gas[0] - 1.0);
-  g.mu_ref = gas[1];
-  g.T_ref = gas[2];
-  g.mu_exp = gas[3];
-  g.Pr = gas[4];
-  double dql[3][5], dqr[3][5];
-  std::memcpy(dql, d, sizeof(dql));
-  std::memcpy(dqr, d + 15, sizeof(dqr));
-  gp_flux_lean(ql, qr, dql, dqr, dq0n, g, dt1, dt2, F1, F2);
-}
-
 /* WENO pieces. where: 0 -> s = 1/2, 1 -> -sqrt3/6, 2 -> +sqrt3/6. */
 void hgo_wenoz(const double v[5], int where, double out[2]) { wenoz(v, where, out[0], out[1]); }
 double hgo_linear_value(const double v[5], int where) { return linear_value(v, where); }
@@ -1427,15 +1239,13 @@ double hgo_step_force(const hgo_config* cfg, double* q, int nsteps, double dt_fi
 double hgo_step(const hgo_config* cfg, double* q, int nsteps, double dt_fixed) {
   return hgo_step_force(cfg, q, nsteps, dt_fixed, nullptr);
 }
-/* One S2O4 stage pair on a scalar linear ODE q' = lam q with exact L and dL/dt
- * (for the amplification-polynomial pin): returns q^{n+1}.                   */
+/* The grid step's two stages (s2o4_stage1, s2o4_stage2) on a scalar linear
+ * ODE q' = lam q, whose L = lam q and dL/dt = lam^2 q are exact (for the
+ * amplification-polynomial pin): returns q^{n+1}.                            */
 double hgo_s2o4_scalar(double q, double lam, double dt) {
-  double L = lam * q, dL = lam * lam * q;
-  double qs = q + 0.5 * dt * L + 0.125 * dt * dt * dL;
-  double acc = q + dt * L + dt * dt / 6.0 * dL;
-  double L2 = lam * qs, dL2 = lam * lam * qs;
-  (void)L2;
-  return acc + dt * dt / 3.0 * dL2;
+  double qs, acc;
+  s2o4_stage1(q, lam * q, lam * lam * q, dt, qs, acc);
+  return s2o4_stage2(acc, lam * lam * qs, dt);
 }
 /* out: Ek, eps_sol, eps_dil, eps_com, total[5], max_abs[5], min_p, min_rho, nonfinite */
 void hgo_stats(const hgo_config* cfg, const double* q, double rho0, double out[17]) {
@@ -1465,9 +1275,8 @@ void hgo_geometry(const hgo_config* cfg, int axis, double* h, double* xc, double
  * out[0] normal sweep per face, out[1] first tangential sweep per (face, GP
  * line), out[2] second tangential sweep per GP, out[3] flux per GP, out[4]
  * face assembly (Gauss sum, F and dF/dt), out[5..11] the per-GP-flux
- * breakdown add, mul, div, sqrt, exp, erfc, pow, and out[12] the per-GP flux
- * in the economical evaluation (u separated from v, w, xi).                 */
-void hgo_count_flops(double out[13]) {
+ * breakdown add, mul, div, sqrt, exp, erfc, pow.                           */
+void hgo_count_flops(double out[12]) {
   using C = Counted;
   /* a smooth, generic state: no zero data, so no branch is skipped */
   double cells[6][5];
@@ -1530,25 +1339,6 @@ void hgo_count_flops(double out[13]) {
   out[3] = total(g_ops);
   out[5] = g_ops.add; out[6] = g_ops.mul; out[7] = g_ops.div; out[8] = g_ops.sqrt;
   out[9] = g_ops.exp; out[10] = g_ops.erfc; out[11] = g_ops.pow;
-  /* the same Gauss-point flux, economical evaluation */
-  g_ops = OpCount();
-  {
-    C ql[5], qr[5], dql[3][5], dqr[3][5], dq0n[5];
-    for (int k = 0; k < 5; ++k) {
-      ql[k] = cells[2][k];
-      qr[k] = cells[3][k] * 1.001;
-      dq0n[k] = 0.01 * (k + 1) * 10.0;
-      for (int d = 0; d < 3; ++d) {
-        dql[d][k] = 0.02 * (k + 1) * (d + 1) * 10.0;
-        dqr[d][k] = 0.021 * (k + 1) * (d + 1) * 10.0;
-      }
-    }
-    Gas<C> gas;
-    gas.gamma = 1.4; gas.K = 2.0; gas.mu_ref = 1e-3; gas.T_ref = 1.0; gas.mu_exp = 0.0; gas.Pr = 0.72;
-    C F1[5], F2[5];
-    gp_flux_lean(ql, qr, dql, dqr, dq0n, gas, C(1e-3), C(0.5e-3), F1, F2);
-  }
-  out[12] = total(g_ops);
   /* face assembly: 4-point sums (2 x 15 adds), area, F and dF/dt (counted by hand:
    * per component 2 sums of 4 -> 6 adds; I1, I2: 2 mul each incl. area; F: 1 mul,
    * 1 add, 1 div; dF: 1 mul, 1 add, 1 mul, 1 mul, 1 div) */

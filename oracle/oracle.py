@@ -94,7 +94,6 @@ def lib():
         L.hgo_time_coefficients.argtypes = [d, d, _D]
         L.hgo_q0.argtypes = [_D, _D, d, _D]
         L.hgo_gp_flux.argtypes = [_D, _D, _D, _D, _D, d, d, _D, _D]
-        L.hgo_gp_flux_lean.argtypes = [_D, _D, _D, _D, _D, d, d, _D, _D]
         L.hgo_wenoz.argtypes = [_D, i, _D]
         L.hgo_linear_value.argtypes = [_D, i]
         L.hgo_linear_value.restype = d
@@ -188,17 +187,6 @@ def gp_flux(ql, qr, dql, dqr, dq0n, gamma=1.4, mu_ref=0.0, T_ref=1.0, mu_exp=0.0
     F1, F2 = np.zeros(5), np.zeros(5)
     lib().hgo_gp_flux(_ptr(_a(ql, 5)), _ptr(_a(qr, 5)), _ptr(d), _ptr(_a(dq0n, 5)), _ptr(gas),
                       float(dt1), float(dt2), _ptr(F1), _ptr(F2))
-    return F1, F2
-
-
-def gp_flux_lean(ql, qr, dql, dqr, dq0n, gamma=1.4, mu_ref=0.0, T_ref=1.0, mu_exp=0.0, Pr=1.0, dt1=1e-3,
-                 dt2=5e-4):
-    """Same flux, economical moment evaluation (for operation counts)."""
-    d = np.concatenate([_a(dql, 15), _a(dqr, 15)])
-    gas = _a([gamma, mu_ref, T_ref, mu_exp, Pr, 0.0], 6)
-    F1, F2 = np.zeros(5), np.zeros(5)
-    lib().hgo_gp_flux_lean(_ptr(_a(ql, 5)), _ptr(_a(qr, 5)), _ptr(d), _ptr(_a(dq0n, 5)), _ptr(gas),
-                           float(dt1), float(dt2), _ptr(F1), _ptr(F2))
     return F1, F2
 
 
@@ -334,14 +322,16 @@ def geometry(p: dict, axis: int):
 
 
 def count_flops() -> dict:
-    out = np.zeros(13)
+    """Operations of the plain (fully expanded) evaluation, counted by the
+    oracle's counting scalar: every add, multiply, divide, square root and
+    transcendental counts one."""
+    out = np.zeros(12)
     lib().hgo_count_flops(_ptr(out))
     return {
         "normal_sweep_per_face": out[0],
         "tangential_1_per_face_gp_line": out[1],
         "tangential_2_per_gp": out[2],
         "flux_per_gp": out[3],
-        "flux_per_gp_lean": out[12],
         "face_assembly": out[4],
         "flux_breakdown": dict(zip(["add", "mul", "div", "sqrt", "exp", "erfc", "pow"], out[5:12].tolist())),
     }

@@ -139,3 +139,75 @@ def time_factor_integrals(tau, delta):
         lambda t: -tau * math.exp(-t / tau),
     ]
     return np.array([_quad(f, 0.0, delta) for f in fs])
+
+
+def equilibrium_and_slopes(ql, qr, dql, dqr, dq0n, K=2, gamma=1.4):
+    """Interface equilibrium and every micro-slope of the BGK solution at one
+    Gauss point, by quadrature tables and dense solves only:
+    Q0 from the compatibility condition (half-space integrals of the left and
+    right Maxwellians), spatial slopes a from <(a . psi) psi> = dQ / rho,
+    tangential slopes of Q0 as the derivative of the compatibility map,
+    time slopes A from <a_n u + a_t1 v + a_t2 w + A> = 0 (full moments)."""
+    pl, pr = primitive(ql, gamma), primitive(qr, gamma)
+    tl_h, tr_h = Table(*pl, K=K, side=1), Table(*pr, K=K, side=-1)
+    tl_f, tr_f = Table(*pl, K=K, side=0), Table(*pr, K=K, side=0)
+    q0 = pl[0] * vec(tl_h, ONE) + pr[0] * vec(tr_h, ONE)
+    p0 = primitive(q0, gamma)
+    t0 = Table(*p0, K=K, side=0)
+    al = [np.linalg.solve(gram(tl_f), np.asarray(dql[d], float) / pl[0]) for d in range(3)]
+    ar = [np.linalg.solve(gram(tr_f), np.asarray(dqr[d], float) / pr[0]) for d in range(3)]
+    dq0 = [np.asarray(dq0n, float)]
+    for d in (1, 2):
+        dq0.append(pl[0] * vec(tl_h, dot_psi(al[d])) + pr[0] * vec(tr_h, dot_psi(ar[d])))
+    a0 = [np.linalg.solve(gram(t0), dq0[d] / p0[0]) for d in range(3)]
+
+    def time_slope(tab, a):
+        rhs = -vec(tab, padd(*[pmul(S_DIR[d], dot_psi(a[d])) for d in range(3)]))
+        return np.linalg.solve(gram(tab), rhs)
+
+    return {
+        "q0": q0, "p0": p0, "pl": pl, "pr": pr,
+        "t0": t0, "tl_h": tl_h, "tr_h": tr_h,
+        "a0": a0, "al": al, "ar": ar,
+        "A0": time_slope(t0, a0), "Al": time_slope(tl_f, al), "Ar": time_slope(tr_f, ar),
+    }
+
+
+def bgk_flux(ql, qr, dql, dqr, dq0n, delta, mu_ref, T_ref=1.0, mu_exp=0.0, Pr=1.0, K=2, gamma=1.4):
+    """Time-integrated flux int_0^delta int u psi f at one Gauss point of the
+    BGK solution of Sec. 2, Eq. (flux), evaluated term by term:
+
+      f = (1 - e) g0 + ((t + tau) e - tau) (sum_d s_d a0_d . psi) g0 + (t - tau + tau e) (A0 . psi) g0
+        + e [1 - (t + tau) (sum_d s_d al_d . psi) - tau (Al . psi)] g_l H(u)
+        + e [1 - (t + tau) (sum_d s_d ar_d . psi) - tau (Ar . psi)] g_r (1 - H(u)),
+
+    e = exp(-t / tau), s = (u, v, w), each time factor integrated over
+    [0, delta] by quadrature and each velocity moment an explicit polynomial
+    expansion on quadrature moment tables.  tau = mu(T0) / p0 from the
+    equilibrium state.  With Pr != 1 the energy flux gains (1/Pr - 1) q, q
+    the same time integral of int c_n (|c|^2 + xi^2)/2 f, c = (u, v, w) - U0
+    (the heat flux in the frame of the equilibrium velocity).  Shares nothing
+    with the oracle."""
+    s = equilibrium_and_slopes(ql, qr, dql, dqr, dq0n, K=K, gamma=gamma)
+    rho0, U0, lam0 = s["p0"][0], s["p0"][1:4], s["p0"][4]
+    T0 = 1.0 / (2.0 * lam0)
+    mu = mu_ref * (T0 / T_ref) ** mu_exp if mu_exp != 0.0 else mu_ref
+    tau = mu / (rho0 * T0)
+    C = time_factor_integrals(tau, delta)
+
+    def transport(a):
+        return padd(*[pmul(S_DIR[d], dot_psi(a[d])) for d in range(3)])
+
+    terms = []
+    for rho, tab, a, A, c in ((rho0, s["t0"], s["a0"], s["A0"], C[0:3]),
+                              (s["pl"][0], s["tl_h"], s["al"], s["Al"], C[3:6]),
+                              (s["pr"][0], s["tr_h"], s["ar"], s["Ar"], C[3:6])):
+        terms += [(rho * c[0], tab, ONE), (rho * c[1], tab, transport(a)), (rho * c[2], tab, dot_psi(A))]
+    F = sum(w * vec(tab, pmul(U_, poly)) for w, tab, poly in terms)
+    cv = [padd(S_DIR[d], pscale(ONE, -U0[d])) for d in range(3)]
+    energy = pscale(padd(pmul(cv[0], cv[0]), pmul(cv[1], cv[1]), pmul(cv[2], cv[2]), XI2), 0.5)
+    heat = pmul(cv[0], energy)
+    q = sum(w * tab.of(pmul(heat, poly)) for w, tab, poly in terms)
+    F = np.array(F, dtype=float)
+    F[4] += (1.0 / Pr - 1.0) * q
+    return F, tau

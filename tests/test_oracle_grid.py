@@ -275,3 +275,99 @@ def test_mass_flux_controller_holds_channel_momentum(oracle):
     # Poiseuille profile, f = 3 mu U_b / h^2 (h = 1, U_b = 1)
     f_lam = 3.0 * p["mu_ref"] * 1.0
     assert abs(f - f_lam) < 0.03 * f_lam, (f, f_lam)
+
+
+def _wall_layer_flux(oracle, ny, T_of_y, U_of_y, mu=2e-3, Pr=0.7):
+    """F^n per unit area through the lower wall (y = -1, uniform y spacing) for
+    a state at uniform pressure 1 with temperature T(y) and streamwise
+    velocity U(y) sampled at the cell centres, constant viscosity."""
+    p = W.channel_params((4, ny, 4), y_stretch=0.0)
+    p.update(mu_ref=mu, mu_exp=0.0, prandtl=Pr, body_force=(0.0, 0.0, 0.0))
+    y = W.channel_y_centres(p)
+    nx, _, nz = p["n"]
+    f = lambda a: np.broadcast_to(np.asarray(a, float)[None, :, None], (nz, ny, nx)).copy()
+    T = T_of_y(y, p["T_wall"])
+    q = np.ascontiguousarray(W.conserved(f(1.0 / T), f(U_of_y(y)), f(0 * y), f(0 * y), f(1.0 + 0 * y)))
+    out = oracle.face_flux(p, q, 1e-5, 1, 0, 1, 1)  # y face 0 (the wall), x/z cell (1, 1)
+    area = (2 * np.pi / nx) * (np.pi / nz)
+    return out[:5] / area, p
+
+
+def test_isothermal_wall_heat_flux_is_fourier(oracle):
+    """R17 (Sec. 4.2 isothermal walls): at rest, uniform pressure and a first
+    cell hotter than the wall, with T rising linearly from T_w at the wall, the
+    energy flux through the wall face is Fourier's -gamma/(gamma - 1) mu/Pr
+    dT/dy against the wall temperature, to second order in the wall-normal
+    spacing (the cell values are point samples).  A ghost rule that does not
+    extrapolate the temperature through T_w (e.g. 2 T_m - T_w) gives an O(1)
+    error here; every other wall pin starts from T = T_w, where the rule is
+    inactive."""
+    G, mu, Pr = 0.3, 2e-3, 0.7
+    errs = []
+    for ny in (32, 64):
+        F, p = _wall_layer_flux(oracle, ny, lambda y, Tw: Tw + G * (y + 1.0), lambda y: 0 * y, mu, Pr)
+        g = p["gamma"]
+        ref = -g / (g - 1.0) * mu / Pr * G
+        errs.append(abs(F[4] - ref) / abs(ref))
+        # no mass or x-momentum through the wall (the ghost density differs from
+        # the interior's once T != T_w, so the mass flux is small, not zero)
+        assert abs(F[0]) <= 1e-6 * abs(ref) and abs(F[1]) <= 1e-12 * abs(ref)
+    print("wall heat flux relative error (ny 32, 64):", errs)
+    assert errs[0] <= 2e-5 and errs[1] <= 5e-6 and errs[0] / errs[1] >= 3.5, errs
+
+
+def test_isothermal_wall_shear_is_newton(oracle):
+    """R17: the no-slip mirror (velocity reversed in the ghost layers) extends
+    a linear wall-bounded profile U = S (y + 1) exactly, so the wall shear
+    stress (x-momentum flux through the wall face) is -mu S to rounding."""
+    S, mu = 0.5, 2e-3
+    F, _ = _wall_layer_flux(oracle, 32, lambda y, Tw: Tw + 0 * y, lambda y: S * (y + 1.0), mu)
+    assert abs(F[1] - (-mu * S)) <= 1e-12 * mu * S, F[1]
+
+
+def _manufactured_channel_field(x, y, z):
+    """A velocity field that vanishes on both walls and is odd about each (so
+    the no-slip mirror continues it smoothly) but not periodic across them,
+    with its exact |curl U|^2 and (div U)^2."""
+    e = y + 1.0
+    s, ds = np.sin(0.5 * np.pi * e), 0.5 * np.pi * np.cos(0.5 * np.pi * e)
+    U = s * np.cos(2 * z)
+    V = 0.5 * s * np.sin(x)
+    Wv = 0.3 * s * np.cos(x)
+    wx = 0.3 * ds * np.cos(x)
+    wy = -2.0 * s * np.sin(2 * z) + 0.3 * s * np.sin(x)
+    wz = 0.5 * s * np.cos(x) - ds * np.cos(2 * z)
+    div = 0.5 * ds * np.sin(x)
+    return U, V, Wv, wx * wx + wy * wy + wz * wz, div * div
+
+
+def test_statistics_on_walled_stretched_grid(oracle):
+    """R20 on the channel grid (Sec. 4.2: tanh-stretched y, isothermal walls):
+    volume means of |U|^2/2, |curl U|^2 and (div U)^2 of a manufactured field
+    against their exact values (numerical quadrature of the analytic
+    derivatives), converging with the grid.  Pins the statistics' wall ghosts
+    (velocity reversed) and the stretched metric: with the ghosts not reversed
+    or the metric of a uniform grid, the near-wall gradients are O(1) wrong."""
+    nq = 64
+    xq = np.arange(nq) * 2 * np.pi / nq
+    zq = np.arange(nq) * np.pi / nq
+    gy, gw = np.polynomial.legendre.leggauss(400)
+    X, Y, Z = np.meshgrid(xq, gy, zq, indexing="ij")
+    U, V, Wv, ens, dil = _manufactured_channel_field(X, Y, Z)
+    mean = lambda a: float((a * gw[None, :, None] / 2.0).sum() / (nq * nq))
+    ref = {"Ek": mean(0.5 * (U * U + V * V + Wv * Wv)), "eps_sol": mean(ens), "eps_dil": 4.0 / 3.0 * mean(dil)}
+    errs = []
+    for ny in (32, 64):
+        p = W.channel_params((32, ny, 32), y_stretch=2.0)
+        p.update(mu_ref=1.0, mu_exp=0.0)
+        nx, _, nz = p["n"]
+        x = (np.arange(nx) + 0.5) * 2 * np.pi / nx
+        z = (np.arange(nz) + 0.5) * np.pi / nz
+        Zc, Yc, Xc = np.meshgrid(z, W.channel_y_centres(p), x, indexing="ij")
+        U, V, Wv, _, _ = _manufactured_channel_field(Xc, Yc, Zc)
+        one = np.ones_like(U)
+        st = oracle.stats(p, np.ascontiguousarray(W.conserved(one, U, V, Wv, one)), 1.0)
+        errs.append({k: abs(st[k] - ref[k]) / ref[k] for k in ref})
+    print("walled-grid statistics relative errors (ny 32, 64):", errs)
+    for k in ref:
+        assert errs[0][k] <= 1e-3 and errs[1][k] <= 3.5e-4, (k, errs)

@@ -246,17 +246,48 @@ def test_chapman_enskog_heat_flux(oracle, Pr):
     assert abs(Fn[4] - ref) <= 1e-11 * abs(ref), (Fn[4], ref)
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-@pytest.mark.parametrize("mu,Pr", [(0.0, 1.0), (2e-3, 0.72), (0.5, 0.7)])
-def test_lean_flux_equals_plain_flux(oracle, seed, mu, Pr):
-    """The economical evaluation (u separated from v, w, xi) whose operations
-    define the algorithmic FLOP count returns the plain evaluation's flux."""
+def _random_gp_inputs(seed):
+    """Distinct left/right states and distinct, non-zero slopes of every kind."""
     rng = np.random.default_rng(seed)
     ql = _q_of((1.0 + 0.1 * rng.uniform(-1, 1), *rng.uniform(-0.5, 0.5, 3), 0.5 + 0.3 * rng.uniform()))
     qr = _q_of((1.0 + 0.1 * rng.uniform(-1, 1), *rng.uniform(-0.5, 0.5, 3), 0.5 + 0.3 * rng.uniform()))
     dql, dqr = rng.uniform(-0.3, 0.3, (3, 5)), rng.uniform(-0.3, 0.3, (3, 5))
     dq0n = rng.uniform(-0.3, 0.3, 5)
-    a1, a2 = oracle.gp_flux(ql, qr, dql, dqr, dq0n, mu_ref=mu, Pr=Pr, dt1=0.02, dt2=0.01)
-    b1, b2 = oracle.gp_flux_lean(ql, qr, dql, dqr, dq0n, mu_ref=mu, Pr=Pr, dt1=0.02, dt2=0.01)
-    np.testing.assert_allclose(b1, a1, rtol=1e-12, atol=1e-14)
-    np.testing.assert_allclose(b2, a2, rtol=1e-12, atol=1e-14)
+    return ql, qr, dql, dqr, dq0n
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("tau_over_dt,Pr,mu_exp", [(0.02, 1.0, 0.0), (0.7, 0.72, 0.0), (6.0, 0.7, 0.0),
+                                                   (0.7, 0.7, 0.7)])
+def test_gp_flux_full_bgk_solution(oracle, seed, tau_over_dt, Pr, mu_exp):
+    """Eq. (flux) with tau > 0, Q_l != Q_r and distinct left/right slopes
+    along n, t1 and t2: the oracle's time-integrated Gauss-point flux over
+    [0, dt] and [0, dt/2] equals the term-by-term quadrature of the BGK
+    solution (kinetic_ref.bgk_flux: half-space and full moment tables by
+    quadrature, polynomial algebra, dense slope solves, time factors by
+    quadrature, heat flux in the frame of U0 for the Prandtl correction).
+    This pins the non-equilibrium g_l / g_r terms (C4..C6, with their own
+    half-space tables and slopes) and the equilibrium terms alike."""
+    ql, qr, dql, dqr, dq0n = _random_gp_inputs(seed)
+    dt, T_ref = 0.02, 0.8
+    s = kr.equilibrium_and_slopes(ql, qr, dql, dqr, dq0n)
+    T0 = 1.0 / (2.0 * s["p0"][4])
+    p0 = s["p0"][0] * T0
+    mu = tau_over_dt * dt * p0 / ((T0 / T_ref) ** mu_exp)  # tau = mu(T0) / p0 = tau_over_dt * dt
+    F1, F2 = oracle.gp_flux(ql, qr, dql, dqr, dq0n, mu_ref=mu, T_ref=T_ref, mu_exp=mu_exp, Pr=Pr,
+                            dt1=dt, dt2=dt / 2)
+    for F, delta in ((F1, dt), (F2, dt / 2)):
+        ref, tau = kr.bgk_flux(ql, qr, dql, dqr, dq0n, delta, mu_ref=mu, T_ref=T_ref, mu_exp=mu_exp, Pr=Pr)
+        assert abs(tau - tau_over_dt * dt) <= 1e-13 * tau
+        np.testing.assert_allclose(F, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+def test_gp_flux_left_right_terms_not_interchangeable(oracle):
+    """The left and right non-equilibrium terms enter with their own slopes:
+    exchanging the two sides' slopes changes the flux by far more than the
+    pin's tolerance, so the pin above distinguishes them."""
+    ql, qr, dql, dqr, dq0n = _random_gp_inputs(5)
+    dt = 0.02
+    F1, _ = oracle.gp_flux(ql, qr, dql, dqr, dq0n, mu_ref=0.3, Pr=0.72, dt1=dt, dt2=dt / 2)
+    ref_swapped, _ = kr.bgk_flux(ql, qr, dqr, dql, dq0n, dt, mu_ref=0.3, Pr=0.72)
+    assert np.abs(F1 - ref_swapped).max() > 1e-6 * np.abs(F1).max()
