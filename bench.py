@@ -5,9 +5,12 @@ a full S2O4 step (two stages, each: three directions of reconstruction and
 flux, then the cell update; CFL time step reduced on the device).
 
 Prints one JSON line.  `roofline` reports the dominant kernel (the flux
-kernel: second tangential sweep, Gauss-point BGK flux, face assembly) against
-the FP64 vector ALU peak, with its duration measured by HIP events on the
-library's stream over the timed region.  `cpu_baseline` times the oracle
+kernel: second tangential sweep, Gauss-point BGK flux, face assembly): the
+floating-point operations it executes (hardware counters of the same build)
+over its duration, measured by HIP events on the library's stream over the
+timed region, against the FP64 vector ALU peak (FP32 for the mixed path).
+`hbm_roofline` is the metric's HBM figure: the bytes the method must move per
+step (120 per cell-stage) over the step time.  `cpu_baseline` times the oracle
 (plain FP64 CPU implementation) on a bounded sample of the same workload.
 `repeats` lists the FP64 path's ms/step over the timed block and further
 blocks of the same number of steps (their median and run-to-run spread).
@@ -29,16 +32,24 @@ if ROOT not in sys.path:
 METRIC = "cell-stage updates/s, 256^3 TGV: FP64 vs mixed-FP32 at stated error; % HBM roofline"
 UNIT = "cell-stage updates/s"
 
-# Floating-point operations of the method per face, counted once (no halo
-# recomputation) by the oracle's counting scalar (oracle.count_flops(); kept in
-# step with it by tests/test_bench_constants.py): second tangential sweep plus
-# Gauss-point flux for 4 Gauss points, plus the face assembly, with the moments
-# evaluated economically (u separated from v, w, xi; the plain expansion of
-# every moment would count 66491).  Every add, multiply, divide, square root
-# and transcendental counts as one operation.
-FLOPS_FLUX_PER_FACE = 30875.0
-# normal sweep plus first tangential sweep (2 Gauss lines) per face
-FLOPS_RECON_PER_FACE = 6630.0
+# Floating-point operations the flux kernel executes per Gauss point (one
+# lane), from rocprofv3 --pmc SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F64,F32} over
+# whole dispatches of the 256^3 TGV: 64 x (ADD + MUL + TRANS + 2 FMA) per wave
+# instruction, divided by the lanes the dispatch launched
+# (profiles/flux_executed_flops_tgv256.md; tests/test_bench_constants.py keeps
+# the two in step).  The roofline credits only the lanes of real faces (4 per
+# face), so the padded lanes of ragged tiles count for nothing.  Valid for the
+# kernel sources they were measured on: `flop_counts_current` says whether the
+# sources still hash to those.
+FLUX_EXECUTED = {
+    "sources_sha256": "2f3ae3d7d071855fbbc8642ded37be322764303c3b452513b7d5bba1ab0afe43",
+    "fp64_flop_per_gp": 4796.0,   # FP64 flux kernel (its FP32 operations: 4 per lane)
+    "fp32_flop_per_gp": 4316.0,   # FP32 flux kernel of the mixed path (plus 42 FP64 per lane)
+}
+# Bytes the method must move per cell-stage (FP64 state): stage 1 reads Q^n
+# and writes Q* and the S2O4 accumulator, stage 2 reads Q* and the
+# accumulator and writes Q^{n+1}: 6 x 40 B per step, 120 B per cell-stage.
+ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 
 # HBM traffic of one flux-kernel launch at 256^3 from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, per dispatch), each divided by the ratio the
@@ -458,8 +469,12 @@ def main() -> int:
             raise RuntimeError(f"{prec_name}: state became invalid during the benchmark")
         flux_ms, flux_n = prof["flux"]
         faces_per_launch = (n + 1) * n * n
-        achieved = FLOPS_FLUX_PER_FACE * faces_per_launch / (flux_ms / flux_n / 1e3) / 1e12
-        peak = PEAK_FP64_VECTOR_TFLOPS if prec == hgks.FP64 else PEAK_FP32_VECTOR_TFLOPS
+        launch_s = flux_ms / flux_n / 1e3
+        fp64 = prec == hgks.FP64
+        flop_per_gp = FLUX_EXECUTED["fp64_flop_per_gp" if fp64 else "fp32_flop_per_gp"]
+        achieved = flop_per_gp * 4 * faces_per_launch / launch_s / 1e12
+        peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
+        traffic = measured_traffic(n) if fp64 else None
         roofline = {
             "bound": "alu",
             "kernel": "flux_kernel (2nd tangential WENO-Z sweep + Gauss-point BGK flux + face assembly)",
@@ -467,12 +482,22 @@ def main() -> int:
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(n) if prec == hgks.FP64 else None,
-            "avg_launch_ms": round(flux_ms / flux_n, 4),
-            "flops_per_face": FLOPS_FLUX_PER_FACE,
+            "traffic": traffic,
+            "flops": "executed " + ("FP64" if fp64 else "FP32") + " operations per Gauss point from the "
+                     "SQ_INSTS_VALU_* counters (FMA = 2), times 4 Gauss points per face",
+            "flop_per_gauss_point": flop_per_gp,
+            "flop_counts_current": FLUX_EXECUTED["sources_sha256"] == kernel_sources_sha256(),
             "faces_per_launch": faces_per_launch,
+            "avg_launch_ms": round(launch_s * 1e3, 4),
             "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
         }
+        if not fp64:
+            # the build excludes packed FP32 instructions: one FP32 operation
+            # per lane and cycle, the rate of FP64
+            roofline["frac_of_unpacked_fp32_peak"] = round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4)
+        if traffic:
+            roofline["traffic_GBs"] = round(traffic / launch_s / 1e9, 1)
+            roofline["traffic_frac_of_hbm_peak"] = round(traffic / launch_s / 1e9 / PEAK_HBM_GBS, 4)
         elapsed = t1 - t0
         state = solver.state()
         spread = None
@@ -518,6 +543,21 @@ def main() -> int:
             "simulated_time": st["t"],
         },
         "roofline": roofline,
+        # the metric's HBM figure: bytes the method must move per step over the step time
+        "hbm_roofline": {
+            "bytes_per_cell_stage": ALGORITHMIC_BYTES_PER_CELL_STAGE,
+            "achieved": round(ALGORITHMIC_BYTES_PER_CELL_STAGE * value / 1e9, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(ALGORITHMIC_BYTES_PER_CELL_STAGE * value / 1e9 / PEAK_HBM_GBS, 5),
+        },
+        # the paper's FP64 single-GPU speedups over its 8-core OpenMP CPU code
+        # (TGV, Sec. 4.1 Table 3): context only, other hardware and code
+        "paper_context": {
+            "fp64_speedup_vs_8core_cpu": {"TITAN RTX": "6.0-7.6 (7x)", "Tesla V100": "15.4-16.1 (16x)"},
+            "cpu": "Intel i7-9700, 8 cores, OpenMP",
+            "v100_256cubed_cell_stage_updates_per_s": 1.79e7,
+        },
     }
     if spread:
         out["repeats"] = spread
@@ -546,6 +586,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_steps)
+        out["paper_context"]["this_gpu_fp64_vs_oracle_on_host"] = round(value / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
     return 0
 
