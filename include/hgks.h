@@ -19,7 +19,8 @@
  * through PyTorch).  The state array q_dev is float64 SoA [5][nz][ny][nx],
  * x fastest, and always holds the latest state once the stream has drained.
  * The workspace is an opaque device buffer of hgks_workspace_size() bytes,
- * 256-byte aligned.  The library allocates only its host-side context.
+ * 256-byte aligned.  The library allocates only its host-side context (and
+ * nothing at all in hgks_residual_static).
  *
  * Streams: all device work of a context is enqueued on the hipStream_t given
  * to hgks_init (passed as void*).  hgks_step is asynchronous; hgks_stats,
@@ -144,6 +145,34 @@ hgks_status hgks_dt(hgks_ctx ctx, double* dt_out);
  * workspace; synchronises the stream. */
 hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* L_dev, double* dL_dev);
 
+/* hgks_residual without a context or a workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): computes on hip_stream (NULL: the default
+ * stream; it must belong to the current HIP device) the same L(Q) and dL/dt of
+ * q_dev, a float64 [5][nz][ny][nx] state of configuration cfg, with flux
+ * windows [0, dt] and [0, dt/2], into L_dev and dL_dev (same layout; all three
+ * caller-owned).  The body force is cfg->body_force; the mixed and FP32
+ * precisions reconstruct on deviations from the volume mean of q_dev (what
+ * hgks_residual does on a context initialised with q_dev).
+ * Memory: the library allocates nothing, host or device.  Its face buffers,
+ * metric arrays and scalars live in one static device array of
+ * HGKS_STATIC_SCRATCH_BYTES bytes per GPU, which each GPU the library runs on
+ * holds from the library's load until the process ends; every call on a GPU
+ * reuses that GPU's array.  Calls that overlap on one GPU (two streams, or two
+ * threads) race on it and give undefined results; calls on one stream are
+ * ordered and safe.
+ * Asynchronous: returns after enqueueing (no synchronisation), so it can be
+ * captured in a HIP graph.
+ * Errors (the detail text of the calling thread's last failure:
+ * hgks_last_error(NULL)): HGKS_E_INVALID for an invalid configuration, a null
+ * or misaligned pointer or dt not positive and finite; HGKS_E_UNSUPPORTED for
+ * a grid whose face buffers exceed the static array (a cube of up to 35^3
+ * cells fits in FP64, 44^3 with the FP32 face data of the mixed and FP32
+ * precisions); HGKS_E_DEVICE for a HIP error. */
+#define HGKS_STATIC_SCRATCH_BYTES (64u << 20)
+hgks_status hgks_residual_static(const hgks_config* cfg, const double* q_dev, double dt, double* L_dev,
+                                 double* dL_dev, void* hip_stream);
+
 /* Kernel timing for benchmarks, with HIP events recorded on the context's
  * stream.  enable != 0: every kernel launch made by hgks_step is bracketed by
  * a pair of events.  hgks_profile_read synchronises the stream and returns,
@@ -190,6 +219,8 @@ hgks_status hgks_batch_info(hgks_ctx ctx, int64_t info[8]);
 hgks_status hgks_destroy(hgks_ctx ctx);
 
 const char* hgks_status_string(hgks_status s);
+/* Detail text of the context's last error; with NULL, of the calling thread's
+ * last failed hgks_residual_static call ("null context" if none). */
 const char* hgks_last_error(hgks_ctx ctx);
 
 #ifdef __cplusplus

@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1016,6 +1017,56 @@ __global__ __launch_bounds__(256) void mass_flux_kernel(const double* __restrict
   }
 }
 
+// ---- device-side set-up (the entry point that takes no host buffers) ------
+// Coordinate map of one axis: uniform, or the tanh stretching of Sec. 4.2,
+// x(xi) = lo + (hi - lo) (1 + tanh(b (2 xi/n - 1)) / tanh b) / 2 for the
+// continuous cell index xi in [0, n].
+struct AxisMap {
+  double lo, hi, b;
+  int n, stretched;
+};
+__device__ __forceinline__ double map_coord(const AxisMap& m, double xi) {
+  const double Lh = m.hi - m.lo;
+  if (m.stretched) return m.lo + 0.5 * Lh * (1.0 + tanh(m.b * (2.0 * xi / m.n - 1.0)) / tanh(m.b));
+  return m.lo + Lh * xi / m.n;
+}
+__device__ __forceinline__ double map_dcoord(const AxisMap& m, double xi) {
+  const double Lh = m.hi - m.lo;
+  if (m.stretched) {
+    const double ch = cosh(m.b * (2.0 * xi / m.n - 1.0));
+    return Lh * m.b / (m.n * tanh(m.b) * ch * ch);
+  }
+  return Lh / m.n;
+}
+// Metric arrays of one axis: cell widths h, and d(index)/dx at the faces
+// (df, n + 1), the two Gauss points of each cell (dg) and the centres (dc).
+__global__ __launch_bounds__(256) void geometry_kernel(AxisMap m, double* __restrict__ h, double* __restrict__ df,
+                                                       double* __restrict__ dg, double* __restrict__ dc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m.n) return;
+  const double hu = (m.hi - m.lo) / m.n;
+  df[i] = m.stretched ? 1.0 / map_dcoord(m, double(i)) : 1.0 / hu;
+  if (i == m.n) return;
+  const double r3 = sqrt(3.0) / 6.0;
+  h[i] = m.stretched ? map_coord(m, i + 1.0) - map_coord(m, double(i)) : hu;
+  dg[2 * i] = m.stretched ? 1.0 / map_dcoord(m, i + 0.5 - r3) : 1.0 / hu;
+  dg[2 * i + 1] = m.stretched ? 1.0 / map_dcoord(m, i + 0.5 + r3) : 1.0 / hu;
+  dc[i] = m.stretched ? 1.0 / map_dcoord(m, i + 0.5) : 1.0 / hu;
+}
+
+// Device scalars of a residual evaluation: every field written (the memory
+// keeps whatever an earlier call left there).
+__global__ void residual_scalars_kernel(Scalars* sc, double dt, double force_x, double* __restrict__ qref) {
+  if (threadIdx.x == 0) {
+    Scalars s{};
+    s.dt = dt;
+    s.dt_residual = dt;
+    s.force_x = force_x;
+    *sc = s;
+  }
+  if (threadIdx.x < 5) qref[threadIdx.x] = 0.0;
+}
+
 }  // namespace hgks
 
 // ===========================================================================
@@ -1038,15 +1089,18 @@ bool precision_mixed(const hgks_config& c) { return c.precision == HGKS_MIXED ||
 // The state, stage values and update in FP32 as well.
 bool precision_fp32(const hgks_config& c) { return c.precision == HGKS_FP32; }
 
-Layout make_layout(const hgks_config& c) {
+// Workspace carve of a configuration.  residual_only: just what L and dL/dt
+// of a state need (face buffers, metric arrays, scalars, reduction partials,
+// reference state), without the stage states and the controller's buffers.
+Layout make_layout(const hgks_config& c, bool residual_only = false) {
   Params P{};
   for (int a = 0; a < 3; ++a) { P.n[a] = c.n[a]; P.bc[a] = c.bc[a]; }
   Layout L{};
   size_t off = 0;
   const size_t n3 = (size_t)c.n[0] * c.n[1] * c.n[2];
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-  L.qs = take(5 * n3 * sizeof(double));
-  L.acc = take(5 * n3 * sizeof(double));
+  L.qs = residual_only ? 0 : take(5 * n3 * sizeof(double));
+  L.acc = residual_only ? 0 : take(5 * n3 * sizeof(double));
   size_t nb = 0;
   for (int d = 0; d < 3; ++d) {
     int be[3], bo[3];
@@ -1070,9 +1124,11 @@ Layout make_layout(const hgks_config& c) {
   L.stat_blocks = (int)((n3 + CELL_THREADS - 1) / CELL_THREADS);
   L.part = take(((size_t)L.stat_blocks + 1) * ST_COUNT * sizeof(double));
   L.qref = take(5 * sizeof(double));
-  L.mf = take(2 * sizeof(double));
-  L.mpart = take(((n3 + CELL_THREADS - 1) / CELL_THREADS) * sizeof(double));
-  L.q32 = precision_fp32(c) ? take(5 * n3 * sizeof(float)) : 0;  // FP32 path: working copy of the state
+  if (!residual_only) {
+    L.mf = take(2 * sizeof(double));
+    L.mpart = take(((n3 + CELL_THREADS - 1) / CELL_THREADS) * sizeof(double));
+    L.q32 = precision_fp32(c) ? take(5 * n3 * sizeof(float)) : 0;  // FP32 path: working copy of the state
+  }
   L.total = off;
   return L;
 }
@@ -1096,6 +1152,29 @@ double dcoord(const hgks_config& c, int a, double xi) {
     return Lh * b / (c.n[a] * std::tanh(b) * ch * ch);
   }
   return Lh / c.n[a];
+}
+
+// Kernel parameters of a configuration; the metric pointers are set by the
+// caller once the metric arrays have a place.
+Params make_params(const hgks_config& c) {
+  Params P{};
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = c.n[a];
+    P.bc[a] = c.bc[a];
+    P.force[a] = c.body_force[a];
+  }
+  P.flags = c.flags;
+  P.gamma = c.gamma;
+  P.gm1 = c.gamma - 1.0;
+  P.K = (5.0 - 3.0 * c.gamma) / (c.gamma - 1.0);
+  P.mu_ref = c.mu_ref;
+  P.T_ref = c.T_ref;
+  P.mu_exp = c.mu_exp;
+  P.pr_fix = 1.0 / c.prandtl - 1.0;
+  P.T_wall = c.T_wall;
+  P.iK3 = 1.0 / (P.K + 3.0);
+  P.iT_ref = c.T_ref > 0.0 ? 1.0 / c.T_ref : 0.0;
+  return P;
 }
 
 const char* kStatus[] = {"ok", "invalid argument", "out of memory", "device error", "non-finite state",
@@ -1164,7 +1243,7 @@ static hipError_t prof_end(hgks_ctx ctx) {
   return r;
 }
 
-static hgks_status validate(const hgks_config* c, std::string* why) {
+static hgks_status validate(const hgks_config* c, const char** why) {
   auto bad = [&](const char* m) { if (why) *why = m; return HGKS_E_INVALID; };
   if (!c) return bad("null config");
   if (c->abi_version != HGKS_ABI_VERSION) return bad("abi_version mismatch");
@@ -1210,29 +1289,38 @@ static hgks_status validate(const hgks_config* c, std::string* why) {
     }                                                                                    \
   } while (0)
 
-template <class R, class S>
-static hgks_status launch_fluxes(hgks_ctx ctx, const S* qin, int use_residual_dt) {
-  const Params& P = ctx->P;
-  R* B = static_cast<R*>(ctx->B);
-  const double* qref = ctx->qref;
+// Reconstruction and flux of the three directions of one stage on `stream`
+// (faces of qin -> F[d]); hook(cls) / hook(-1) bracket each launch (the
+// context's profiling events; a no-op elsewhere).
+template <class R, class S, class Hook>
+static hipError_t enqueue_fluxes(const Params& P, hipStream_t stream, const S* qin, R* B, double* const F[3],
+                                 const Scalars* sc, const double* qref, int use_residual_dt, Hook&& hook) {
   auto recon_blocks = [&](int d) {
     return (unsigned)(d == 0 ? recon_tiles<0, R>(P) : (d == 1 ? recon_tiles<1, R>(P) : recon_tiles<2, R>(P)));
   };
   auto flux_blocks = [&](int d) { return (unsigned)flux_tiles<16>(P, d); };
+  hipError_t e;
 #define HGKS_DIRECTION(D)                                                                                    \
-  HIP_TRY(ctx, prof_begin(ctx, PROF_RECON));                                                                 \
-  hipLaunchKernelGGL((recon_kernel<D, R, S>), dim3(recon_blocks(D)), dim3(RECON_THREADS), 0,                 \
-                     ctx->stream, qin, P, qref, B);                                                          \
-  HIP_TRY(ctx, prof_end(ctx));                                                                               \
-  HIP_TRY(ctx, prof_begin(ctx, PROF_FLUX));                                                                  \
-  hipLaunchKernelGGL((flux_kernel<D, R>), dim3(flux_blocks(D)), dim3(FLUX_THREADS), 0, ctx->stream, B, P,   \
-                     qref, ctx->sc, use_residual_dt, ctx->F[D]);                                             \
-  HIP_TRY(ctx, prof_end(ctx));
+  if ((e = hook(PROF_RECON)) != hipSuccess) return e;                                                        \
+  hipLaunchKernelGGL((recon_kernel<D, R, S>), dim3(recon_blocks(D)), dim3(RECON_THREADS), 0, stream, qin, P, \
+                     qref, B);                                                                               \
+  if ((e = hook(-1)) != hipSuccess) return e;                                                                \
+  if ((e = hook(PROF_FLUX)) != hipSuccess) return e;                                                         \
+  hipLaunchKernelGGL((flux_kernel<D, R>), dim3(flux_blocks(D)), dim3(FLUX_THREADS), 0, stream, B, P, qref,  \
+                     sc, use_residual_dt, F[D]);                                                             \
+  if ((e = hook(-1)) != hipSuccess) return e;
   HGKS_DIRECTION(0)
   HGKS_DIRECTION(1)
   HGKS_DIRECTION(2)
 #undef HGKS_DIRECTION
-  HIP_TRY(ctx, hipGetLastError());
+  return hipGetLastError();
+}
+
+template <class R, class S>
+static hgks_status launch_fluxes(hgks_ctx ctx, const S* qin, int use_residual_dt) {
+  auto hook = [ctx](int cls) { return cls >= 0 ? prof_begin(ctx, cls) : prof_end(ctx); };
+  HIP_TRY(ctx, (enqueue_fluxes<R, S>(ctx->P, ctx->stream, qin, static_cast<R*>(ctx->B), ctx->F, ctx->sc,
+                                     ctx->qref, use_residual_dt, hook)));
   return HGKS_OK;
 }
 
@@ -1240,6 +1328,42 @@ static hgks_status launch_fluxes_any(hgks_ctx ctx, const double* qin, int use_re
   if (precision_mixed(ctx->cfg)) return launch_fluxes<float, double>(ctx, qin, use_residual_dt);
   return launch_fluxes<double, double>(ctx, qin, use_residual_dt);
 }
+
+// ---- the residual entry point that allocates nothing --------------------
+// Its face buffers, metric arrays, scalars and reduction partials live in
+// `scratch`, a static device array of HGKS_STATIC_SCRATCH_BYTES: each GPU the
+// library runs on holds its own copy from module load to process exit.  In
+// host code the array's name is a host-side stand-in, not a device address:
+// host code uses only the address hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) unsigned char scratch[HGKS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+thread_local char g_static_err[256] = "";
+
+void static_error(const char* what, const char* detail) {
+  std::snprintf(g_static_err, sizeof(g_static_err), "%s%s%s", what, detail[0] ? ": " : "", detail);
+}
+
+// The current device's copy of `scratch` (looked up once per device).
+hipError_t scratch_on_current_device(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return hipSuccess;
+}
+}  // namespace
 
 static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CELL_THREADS - 1) / CELL_THREADS); }
 
@@ -1495,23 +1619,8 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
   ctx->L = L;
   ctx->latched = HGKS_OK;
   ctx->t0 = t0;
+  ctx->P = make_params(*cfg);
   Params& P = ctx->P;
-  for (int a = 0; a < 3; ++a) {
-    P.n[a] = cfg->n[a];
-    P.bc[a] = cfg->bc[a];
-    P.force[a] = cfg->body_force[a];
-  }
-  P.flags = cfg->flags;
-  P.gamma = cfg->gamma;
-  P.gm1 = cfg->gamma - 1.0;
-  P.K = (5.0 - 3.0 * cfg->gamma) / (cfg->gamma - 1.0);
-  P.mu_ref = cfg->mu_ref;
-  P.T_ref = cfg->T_ref;
-  P.mu_exp = cfg->mu_exp;
-  P.pr_fix = 1.0 / cfg->prandtl - 1.0;
-  P.T_wall = cfg->T_wall;
-  P.iK3 = 1.0 / (P.K + 3.0);
-  P.iT_ref = cfg->T_ref > 0.0 ? 1.0 / cfg->T_ref : 0.0;
   ctx->qs = reinterpret_cast<double*>(ctx->ws + L.qs);
   ctx->acc = reinterpret_cast<double*>(ctx->ws + L.acc);
   ctx->B = ctx->ws + L.B;
@@ -1660,6 +1769,78 @@ hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* 
   return HGKS_OK;
 }
 
+hgks_status hgks_residual_static(const hgks_config* cfg, const double* q_dev, double dt, double* L_dev,
+                                 double* dL_dev, void* hip_stream) {
+  g_static_err[0] = '\0';
+  const char* why = "";
+  if (validate(cfg, &why) != HGKS_OK) {
+    static_error("invalid configuration", why);
+    return HGKS_E_INVALID;
+  }
+  if (!q_dev || !L_dev || !dL_dev || !(dt > 0.0) || !std::isfinite(dt) || ((uintptr_t)q_dev & 7u) != 0) {
+    static_error("invalid argument", "null or misaligned pointer, or dt not positive and finite");
+    return HGKS_E_INVALID;
+  }
+  const Layout L = make_layout(*cfg, true);
+  if (L.total > (size_t)HGKS_STATIC_SCRATCH_BYTES) {
+    char detail[160];
+    std::snprintf(detail, sizeof(detail), "the grid needs %zu bytes of face buffers, more than the %zu of the static array",
+                  L.total, (size_t)HGKS_STATIC_SCRATCH_BYTES);
+    static_error("grid too large for hgks_residual_static", detail);
+    return HGKS_E_UNSUPPORTED;
+  }
+  char* base = nullptr;
+  hipError_t e = scratch_on_current_device(&base);
+  if (e != hipSuccess) {
+    static_error("hipGetSymbolAddress(scratch)", hipGetErrorString(e));
+    return HGKS_E_DEVICE;
+  }
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  Params P = make_params(*cfg);
+  for (int a = 0; a < 3; ++a) {
+    double* h = reinterpret_cast<double*>(base + L.metric[a][0]);
+    double* df = reinterpret_cast<double*>(base + L.metric[a][1]);
+    double* dg = reinterpret_cast<double*>(base + L.metric[a][2]);
+    double* dc = reinterpret_cast<double*>(base + L.metric[a][3]);
+    const AxisMap m{cfg->lo[a], cfg->hi[a], cfg->y_stretch, cfg->n[a], a == 1 && cfg->y_stretch > 0.0};
+    hipLaunchKernelGGL(geometry_kernel, dim3((cfg->n[a] + 256) / 256), dim3(256), 0, stream, m, h, df, dg, dc);
+    P.hcell[a] = h;
+    P.dface[a] = df;
+    P.dgp[a] = dg;
+    P.dcen[a] = dc;
+  }
+  Scalars* sc = reinterpret_cast<Scalars*>(base + L.scal);
+  double* qref = reinterpret_cast<double*>(base + L.qref);
+  double* F[3];
+  for (int d = 0; d < 3; ++d) F[d] = reinterpret_cast<double*>(base + L.F[d]);
+  hipLaunchKernelGGL(residual_scalars_kernel, dim3(1), dim3(64), 0, stream, sc, dt, cfg->body_force[0], qref);
+  auto no_hook = [](int) { return hipSuccess; };
+  if (precision_mixed(*cfg)) {
+    // reference state of the FP32 reconstruction: the volume mean of q_dev
+    double* part = reinterpret_cast<double*>(base + L.part);
+    double* fin = part + (size_t)L.stat_blocks * ST_COUNT;
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= cfg->hi[a] - cfg->lo[a];
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(L.stat_blocks), dim3(CELL_THREADS), 0, stream, q_dev, P, part);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(ST_COUNT), dim3(256), 0, stream, part, L.stat_blocks, fin);
+    hipLaunchKernelGGL(mean_state_kernel, dim3(1), dim3(64), 0, stream, fin, 1.0 / vol, qref);
+    e = enqueue_fluxes<float, double>(P, stream, q_dev, reinterpret_cast<float*>(base + L.B), F, sc, qref, 1, no_hook);
+  } else {
+    e = enqueue_fluxes<double, double>(P, stream, q_dev, reinterpret_cast<double*>(base + L.B), F, sc, qref, 1,
+                                       no_hook);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(residual_kernel, dim3(cell_blocks(P)), dim3(CELL_THREADS), 0, stream, q_dev, F[0], F[1], F[2],
+                       P, sc, L_dev, dL_dev);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    static_error("kernel launch", hipGetErrorString(e));
+    return HGKS_E_DEVICE;
+  }
+  return HGKS_OK;
+}
+
 hgks_status hgks_profile(hgks_ctx ctx, int32_t enable) {
   if (!ctx) return HGKS_E_INVALID;
   ctx->prof = enable != 0;
@@ -1697,7 +1878,10 @@ const char* hgks_status_string(hgks_status s) {
   return kStatus[i];
 }
 
-const char* hgks_last_error(hgks_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* hgks_last_error(hgks_ctx ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_static_err[0] ? g_static_err : "null context";
+}
 
 hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes) {
   if (n <= 0 || !cfgs || !bytes) return HGKS_E_INVALID;

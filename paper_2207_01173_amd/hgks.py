@@ -25,7 +25,9 @@ EXPORTED = [
     "hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
     "hgks_destroy", "hgks_status_string", "hgks_last_error", "hgks_profile", "hgks_profile_read",
     "hgks_batch_workspace_size", "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info",
+    "hgks_residual_static",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20
 PROFILE_CLASSES = ("recon", "flux", "update", "other")
 
 
@@ -94,6 +96,7 @@ def lib():
         L.hgks_stats.argtypes = [vp, ctypes.POINTER(hgks_stats_t)]
         L.hgks_dt.argtypes = [vp, ctypes.POINTER(d)]
         L.hgks_residual.argtypes = [vp, vp, d, vp, vp]
+        L.hgks_residual_static.argtypes = [C, vp, d, vp, vp, vp]
         L.hgks_destroy.argtypes = [vp]
         L.hgks_batch_workspace_size.argtypes = [i32, C, ctypes.POINTER(sz)]
         L.hgks_batch_init.argtypes = [i32, C, ctypes.POINTER(vp), vp, sz, vp, ctypes.POINTER(vp)]
@@ -107,6 +110,7 @@ def lib():
         L.hgks_last_error.argtypes = [vp]
         L.hgks_last_error.restype = ctypes.c_char_p
         for f in ("hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
+                  "hgks_residual_static",
                   "hgks_destroy", "hgks_profile", "hgks_profile_read", "hgks_batch_workspace_size",
                   "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info"):
             getattr(L, f).restype = i32
@@ -185,6 +189,16 @@ def hgks_dt(ctx) -> float:
 def hgks_residual(ctx, q_ptr: int, dt: float, L_ptr: int, dL_ptr: int):
     _check(lib().hgks_residual(ctx, ctypes.c_void_p(q_ptr), float(dt), ctypes.c_void_p(L_ptr),
                                ctypes.c_void_p(dL_ptr)), ctx)
+
+
+def hgks_residual_static(cfg, q_ptr: int, dt: float, L_ptr: int, dL_ptr: int, stream_ptr: int):
+    """L and dL/dt with no context and no workspace (the library's static
+    device array); asynchronous on the stream."""
+    L = lib()
+    st = L.hgks_residual_static(ctypes.byref(cfg), ctypes.c_void_p(q_ptr), float(dt), ctypes.c_void_p(L_ptr),
+                                ctypes.c_void_p(dL_ptr), ctypes.c_void_p(stream_ptr))
+    if st != HGKS_OK:
+        raise HGKSError(st, L.hgks_last_error(None).decode())
 
 
 def hgks_profile(ctx, enable: bool):
