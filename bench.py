@@ -128,26 +128,63 @@ def ensemble_bench(steps: int, precision: str) -> dict:
     tb = time.perf_counter() - t0
     b.close()
     print(f"# batched: {tb:.3f} s; per-instance loop next", file=sys.stderr, flush=True)
-    solvers = [hgks.Solver(p, q, precision=prec) for p, q in zip(params, q0)]
-    for s in solvers:
-        s.step(1, 0.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    def instance_loop(stream):
+        """Every instance advanced one step at a time in turn; on a created
+        stream each hgks_step replays that instance's captured step, on the
+        default stream it launches the kernels one by one."""
+        solvers = [hgks.Solver(p, q, precision=prec, stream=stream) for p, q in zip(params, q0)]
         for s in solvers:
             s.step(1, 0.0)
-    torch.cuda.synchronize()
-    tl = time.perf_counter() - t0
-    for s in solvers:
-        s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for s in solvers:
+                s.step(1, 0.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        for s in solvers:
+            s.close()
+        return t
+
+    tl = instance_loop(None)
+    print(f"# per-instance loop, plain launches: {tl:.3f} s; with graph replays next", file=sys.stderr, flush=True)
+    tg = instance_loop(torch.cuda.Stream())
     cs = 2.0 * cells * steps
     return {
         "metric": "cell-stage updates/s, 64-instance TGV ensemble (N in {24..96}, Ma 0.1-0.5, Re 400-3000)",
         "unit": UNIT, "steps": steps, "precision": precision, "instances": len(params), "cells": cells,
         "batched": {"value": cs / tb, "seconds": tb, "launch_shapes": info},
-        "per_instance_loop": {"value": cs / tl, "seconds": tl},
+        "per_instance_loop": {"value": cs / tl, "seconds": tl, "launches": "kernel by kernel"},
+        "per_instance_loop_graph": {"value": cs / tg, "seconds": tg, "launches": "one captured step per instance"},
         "speedup": tl / tb,
+        "speedup_vs_graph_loop": tg / tb,
     }
+
+
+def small_grid_steps(n: int, steps: int) -> dict:
+    """One TGV instance at n^3 (Ma 0.29): ms per step with the kernels
+    launched one by one (default stream) and with the captured step replayed
+    (a created stream)."""
+    import torch
+
+    from paper_2207_01173_amd import hgks
+    from paper_2207_01173_amd import workloads as W
+
+    p = tgv_workload(n)
+    q0 = W.tgv_initial(p)
+    out = {"metric": f"ms per S2O4 step, TGV {n}^3, FP64: kernel-by-kernel launches vs one HIP-graph replay",
+           "n": n, "steps": steps}
+    for name, stream in (("plain", None), ("graph", torch.cuda.Stream())):
+        s = hgks.Solver(p, q0, stream=stream)
+        s.step(3, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, 0.0)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        s.close()
+    out["speedup"] = out["plain_ms_per_step"] / out["graph_ms_per_step"]
+    return out
 
 
 def tgv_history(n: int, ma: float, t_end: float, every: int, with_mixed: bool = True) -> dict:
@@ -415,6 +452,8 @@ def main() -> int:
     ap.add_argument("--mass-flux", action="store_true", help="--channel with the constant-mass-flux controller")
     ap.add_argument("--ma", type=float, default=0.1, help="Mach number of --history")
     ap.add_argument("--every", type=int, default=10, help="statistics interval of --history (steps)")
+    ap.add_argument("--small-grid", type=int, default=0, metavar="N",
+                    help="instead: ms per step at N^3, kernel by kernel vs one graph replay")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -433,6 +472,9 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.small_grid:
+        print(json.dumps(small_grid_steps(args.small_grid, args.steps)), flush=True)
+        return 0
     if args.ensemble:
         print(json.dumps(ensemble_bench(args.steps, args.precision)), flush=True)
         return 0

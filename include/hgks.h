@@ -130,7 +130,12 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
 
 /* Advance nsteps S2O4 steps (Eq. (two-stage)).  dt_fixed > 0 uses that time
  * step; dt_fixed <= 0 takes dt = cfl / max_cells max_d (|U_d| + c) / h_d from
- * the state at the start of each step.  Asynchronous. */
+ * the state at the start of each step.  Asynchronous.  On a created stream
+ * one step is captured in a HIP graph at the first call and replayed nsteps
+ * times (one launch per step; the time-step rule is a device value, so the
+ * graph serves every dt_fixed); on the default stream, with profiling
+ * enabled, or on a stream the caller is capturing, the kernels are launched
+ * one by one.  Both give bit-identical results. */
 hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed);
 
 /* Statistics of the current state (synchronises the stream). */
@@ -220,7 +225,9 @@ hgks_status hgks_destroy(hgks_ctx ctx);
 
 const char* hgks_status_string(hgks_status s);
 /* Detail text of the context's last error; with NULL, of the calling thread's
- * last failed hgks_residual_static call ("null context" if none). */
+ * last failure that left no context: hgks_init, hgks_batch_init (whose
+ * context is released on failure) or hgks_residual_static ("null context" if
+ * none). */
 const char* hgks_last_error(hgks_ctx ctx);
 
 #ifdef __cplusplus

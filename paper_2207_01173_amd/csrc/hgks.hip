@@ -64,7 +64,7 @@ struct Scalars {
   unsigned long long smax;   // bit pattern of max wave speed / h (positive double)
   double force_x;            // streamwise body force in effect (the controller's, with the mass-flux flag)
   double m_prev;             // volume mean of rho U after the last step (mass-flux controller)
-  double pad;
+  double dt_fixed;           // > 0: the time step of every step; <= 0: the CFL rule
 };
 
 // Global-memory view of a device pointer.  A pointer that a kernel reads out
@@ -772,10 +772,10 @@ __global__ __launch_bounds__(CELL_THREADS) void wave_rate_kernel(const double* _
 
 // Start of a step: choose dt (fixed, or CFL from the wave-speed maximum of
 // the current state), advance the clock, clear the maximum for stage 2.
-__global__ void begin_step_kernel(Scalars* sc, double cfl, double dt_fixed) {
+__global__ void begin_step_kernel(Scalars* sc, double cfl) {
   if (threadIdx.x != 0) return;
   const double smax = __longlong_as_double((long long)sc->smax);
-  const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / smax;
+  const double dt = sc->dt_fixed > 0.0 ? sc->dt_fixed : cfl / smax;
   sc->dt = dt;
   sc->t += dt;
   sc->steps += 1.0;
@@ -974,6 +974,15 @@ __global__ void begin_step_batch_kernel(BatchTable T) {
   sc->t += dt;
   sc->steps += 1.0;
   sc->smax = 0ull;
+}
+
+// Each member's CFL time step from its current wave-speed maximum, nothing
+// else changed (the autotuner's launches then work on real time steps).
+__global__ void batch_cfl_dt_kernel(BatchTable T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T.n) return;
+  Scalars* sc = T.E[i].sc;
+  sc->dt = T.E[i].cfl / __longlong_as_double((long long)sc->smax);
 }
 
 // Reference state of the FP32-reconstruction paths (mixed, FP32): the volume
@@ -1215,8 +1224,10 @@ struct hgks_ctx_s {
   std::vector<int> pre;          // host copy of the prefix rows
   std::vector<int> group_first;  // member groups [group_first[g], group_first[g + 1])
   int tx = 16, group_mib = 0, tune_source = 0;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;      // batched step, or the single-instance step (hgks_step)
   hipGraphExec_t exec = nullptr;
+  double dt_fixed = 0.0;           // last time-step rule written to the device scalars
+  bool dt_fixed_known = false;
 };
 
 enum { PROF_RECON = 0, PROF_FLUX = 1, PROF_UPDATE = 2, PROF_OTHER = 3 };
@@ -1368,13 +1379,14 @@ hipError_t scratch_on_current_device(char** out) {
 static unsigned cell_blocks(const Params& P) { return (unsigned)((cells(P) + CELL_THREADS - 1) / CELL_THREADS); }
 
 // nsteps S2O4 steps on a state of type S (q, qs, acc: the state, Q*, the
-// accumulator), R the reconstruction and flux type.
+// accumulator), R the reconstruction and flux type; the time step rule comes
+// from the device scalars (dt_fixed).
 template <class R, class S>
-static hgks_status step_loop(hgks_ctx ctx, S* q, S* qs, S* acc, int32_t nsteps, double dt_fixed) {
+static hgks_status step_loop(hgks_ctx ctx, S* q, S* qs, S* acc, int32_t nsteps) {
   const Params& P = ctx->P;
   for (int s = 0; s < nsteps; ++s) {
     HIP_TRY(ctx, prof_begin(ctx, PROF_OTHER));
-    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->sc, ctx->cfg.cfl, dt_fixed);
+    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->sc, ctx->cfg.cfl);
     HIP_TRY(ctx, prof_end(ctx));
     hgks_status r = launch_fluxes<R, S>(ctx, q, 0);
     if (r != HGKS_OK) return r;
@@ -1566,6 +1578,9 @@ static hgks_status batch_autotune(hgks_ctx b) {
       std::fclose(f);
     }
   }
+  // the members' CFL time steps, so that the timed flux launches do the
+  // work of a real step (the captured step sets them again every step)
+  hipLaunchKernelGGL(batch_cfl_dt_kernel, dim3((b->table.n + 63) / 64), dim3(64), 0, b->stream, b->table);
   float best = 1e30f, ms = 0.0f;
   int best_tx = 16, best_mib = 0;
   for (int tx : {16, 32}) {
@@ -1589,37 +1604,11 @@ static hgks_status batch_autotune(hgks_ctx b) {
   return HGKS_OK;
 }
 
-extern "C" {
-
-hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes) {
-  if (!bytes) return HGKS_E_INVALID;
-  hgks_status s = validate(cfg, nullptr);
-  if (s != HGKS_OK) return s;
-  *bytes = make_layout(*cfg).total;
-  return HGKS_OK;
-}
-
-hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_t ws_bytes, void* hip_stream,
-                      double t0, hgks_ctx* out) {
-  if (!out) return HGKS_E_INVALID;
-  *out = nullptr;
-  hgks_status s = validate(cfg, nullptr);
-  if (s != HGKS_OK) return s;
-  if (!q_dev || !ws_dev) return HGKS_E_INVALID;
-  if (((uintptr_t)ws_dev & 255u) != 0 || ((uintptr_t)q_dev & 7u) != 0) return HGKS_E_INVALID;
-  Layout L = make_layout(*cfg);
-  if (ws_bytes < L.total) return HGKS_E_INVALID;
-  hgks_ctx ctx = new (std::nothrow) hgks_ctx_s();
-  if (!ctx) return HGKS_E_NOMEM;
-  ctx->cfg = *cfg;
-  ctx->stream = static_cast<hipStream_t>(hip_stream);
-  ctx->q = q_dev;
-  ctx->ws = static_cast<char*>(ws_dev);
-  ctx->ws_bytes = ws_bytes;
-  ctx->L = L;
-  ctx->latched = HGKS_OK;
-  ctx->t0 = t0;
-  ctx->P = make_params(*cfg);
+// Device half of hgks_init: workspace pointers, geometry upload, the first
+// wave-speed reduction and the volume means some paths need.
+static hgks_status init_device(hgks_ctx ctx) {
+  const hgks_config* cfg = &ctx->cfg;
+  const Layout& L = ctx->L;
   Params& P = ctx->P;
   ctx->qs = reinterpret_cast<double*>(ctx->ws + L.qs);
   ctx->acc = reinterpret_cast<double*>(ctx->ws + L.acc);
@@ -1661,7 +1650,7 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
     P.dcen[a] = reinterpret_cast<const double*>(ctx->ws + L.metric[a][3]);
   }
   Scalars s0{};
-  s0.t = t0;
+  s0.t = ctx->t0;
   s0.force_x = cfg->body_force[0];
   double qref[5] = {0, 0, 0, 0, 0};
   HIP_TRY(ctx, hipMemcpyAsync(ctx->sc, &s0, sizeof(Scalars), hipMemcpyHostToDevice, ctx->stream));
@@ -1683,28 +1672,162 @@ hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_
       hipLaunchKernelGGL(mass_flux_init_kernel, dim3(1), dim3(64), 0, ctx->stream, fin, 1.0 / vol, ctx->mf, ctx->sc);
   }
   HIP_TRY(ctx, hipGetLastError());
+  return HGKS_OK;
+}
+
+// Device half of hgks_batch_init: member contexts over slices of the
+// workspace, the device work table, the tuned launch shapes and the captured
+// step.  On failure the caller destroys b (and the members made so far).
+static hgks_status batch_init_body(hgks_ctx b, int n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev,
+                                   void* hip_stream) {
+  char* base = static_cast<char*>(ws_dev);
+  size_t off = 0;
+  std::vector<BatchEntry> host(n);
+  for (int i = 0; i < n; ++i) {
+    const size_t sz = align256(make_layout(cfgs[i]).total);
+    hgks_ctx m = nullptr;
+    hgks_status st = hgks_init(&cfgs[i], q_devs[i], base + off, sz, hip_stream, 0.0, &m);
+    if (st != HGKS_OK) {
+      b->err = "member " + std::to_string(i) + ": " + hgks_last_error(nullptr);
+      return st;
+    }
+    b->members.push_back(m);
+    off += sz;
+    BatchEntry& e = host[i];
+    e.P = m->P;
+    e.q = m->q;
+    e.qs = m->qs;
+    e.acc = m->acc;
+    e.B = m->B;
+    for (int d = 0; d < 3; ++d) e.F[d] = m->F[d];
+    e.sc = m->sc;
+    e.qref = m->qref;
+    e.cfl = cfgs[i].cfl;
+  }
+  b->pre = batch_prefix(n, cfgs);
+  const std::vector<int> coarse = batch_coarse(n, b->pre, b->table.coarse_off);
+  BatchEntry* dE = reinterpret_cast<BatchEntry*>(base + off);
+  off += align256((size_t)n * sizeof(BatchEntry));
+  int* dpre = reinterpret_cast<int*>(base + off);
+  off += align256(b->pre.size() * sizeof(int));
+  int* dcoarse = reinterpret_cast<int*>(base + off);
+  HIP_TRY(b, hipMemcpyAsync(dE, host.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipMemcpyAsync(dpre, b->pre.data(), b->pre.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipMemcpyAsync(dcoarse, coarse.data(), coarse.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(b, hipStreamSynchronize(b->stream));
+  b->table.E = dE;
+  b->table.pre = dpre;
+  b->table.coarse = dcoarse;
+  b->table.n = n;
+  const hgks_status st = batch_autotune(b);
+  if (st != HGKS_OK) return st;
+  // capture one step
+  HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+  enqueue_batch_step(b);
+  HIP_TRY(b, hipStreamEndCapture(b->stream, &b->graph));
+  HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return HGKS_OK;
+}
+
+extern "C" {
+
+hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes) {
+  if (!bytes) return HGKS_E_INVALID;
+  hgks_status s = validate(cfg, nullptr);
+  if (s != HGKS_OK) return s;
+  *bytes = make_layout(*cfg).total;
+  return HGKS_OK;
+}
+
+hgks_status hgks_init(const hgks_config* cfg, double* q_dev, void* ws_dev, size_t ws_bytes, void* hip_stream,
+                      double t0, hgks_ctx* out) {
+  if (!out) return HGKS_E_INVALID;
+  *out = nullptr;
+  hgks_status s = validate(cfg, nullptr);
+  if (s != HGKS_OK) return s;
+  if (!q_dev || !ws_dev) return HGKS_E_INVALID;
+  if (((uintptr_t)ws_dev & 255u) != 0 || ((uintptr_t)q_dev & 7u) != 0) return HGKS_E_INVALID;
+  Layout L = make_layout(*cfg);
+  if (ws_bytes < L.total) return HGKS_E_INVALID;
+  hgks_ctx ctx = new (std::nothrow) hgks_ctx_s();
+  if (!ctx) return HGKS_E_NOMEM;
+  ctx->cfg = *cfg;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->q = q_dev;
+  ctx->ws = static_cast<char*>(ws_dev);
+  ctx->ws_bytes = ws_bytes;
+  ctx->L = L;
+  ctx->latched = HGKS_OK;
+  ctx->t0 = t0;
+  ctx->P = make_params(*cfg);
+  const hgks_status st = init_device(ctx);
+  if (st != HGKS_OK) {
+    // the context dies here: its error text goes to the thread's slot
+    static_error("hgks_init", ctx->err.c_str());
+    delete ctx;
+    return st;
+  }
   *out = ctx;
   return HGKS_OK;
 }
 
+
 hgks_status hgks_step(hgks_ctx ctx, int32_t nsteps, double dt_fixed) {
   if (!ctx || nsteps < 0 || !std::isfinite(dt_fixed) || !ctx->members.empty()) return HGKS_E_INVALID;
   if (ctx->latched != HGKS_OK) return ctx->latched;
-  if (!precision_fp32(ctx->cfg)) {
-    if (precision_mixed(ctx->cfg)) return step_loop<float, double>(ctx, ctx->q, ctx->qs, ctx->acc, nsteps, dt_fixed);
-    return step_loop<double, double>(ctx, ctx->q, ctx->qs, ctx->acc, nsteps, dt_fixed);
+  if (nsteps == 0) return HGKS_OK;
+  // the time-step rule lives on the device, so one captured step serves any dt
+  if (!ctx->dt_fixed_known || ctx->dt_fixed != dt_fixed) {
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, &ctx->sc->dt_fixed, dt_fixed);
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->dt_fixed = dt_fixed;
+    ctx->dt_fixed_known = true;
   }
+  const bool fp32 = precision_fp32(ctx->cfg);
+  const size_t n = 5 * cells(ctx->P);
+  const unsigned g = (unsigned)((n + CELL_THREADS - 1) / CELL_THREADS);
   // FP32 path: the caller's FP64 state in (rounded on the first call, exact
   // afterwards since it then holds FP32 values), the steps on the FP32 working
   // copy, the result back to the caller's state.
-  const size_t n = 5 * cells(ctx->P);
-  const unsigned g = (unsigned)((n + CELL_THREADS - 1) / CELL_THREADS);
-  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->q32, n);
-  float* qs = reinterpret_cast<float*>(ctx->qs);
-  float* acc = reinterpret_cast<float*>(ctx->acc);
-  hgks_status r = step_loop<float, float>(ctx, ctx->q32, qs, acc, nsteps, dt_fixed);
-  if (r != HGKS_OK) return r;
-  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q32, ctx->q, n);
+  if (fp32)
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q, ctx->q32,
+                       n);
+  auto steps = [&](int32_t k) -> hgks_status {
+    if (fp32)
+      return step_loop<float, float>(ctx, ctx->q32, reinterpret_cast<float*>(ctx->qs),
+                                     reinterpret_cast<float*>(ctx->acc), k);
+    if (precision_mixed(ctx->cfg)) return step_loop<float, double>(ctx, ctx->q, ctx->qs, ctx->acc, k);
+    return step_loop<double, double>(ctx, ctx->q, ctx->qs, ctx->acc, k);
+  };
+  hgks_status r = HGKS_OK;
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  if (ctx->stream) HIP_TRY(ctx, hipStreamIsCapturing(ctx->stream, &capturing));
+  if (ctx->stream && !ctx->prof && capturing == hipStreamCaptureStatusNone) {
+    // one S2O4 step captured once in a HIP graph and replayed: one launch per
+    // step instead of 15 (a created stream only: the default stream cannot
+    // be captured; profiling needs the events between plain launches; a
+    // stream the caller is capturing gets plain launches, into its graph)
+    if (!ctx->exec) {
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+      r = steps(1);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+      if (r != HGKS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+      }
+      HIP_TRY(ctx, e);
+      ctx->graph = graph;
+      HIP_TRY(ctx, hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+    }
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(ctx, hipGraphLaunch(ctx->exec, ctx->stream));
+  } else {
+    r = steps(nsteps);
+    if (r != HGKS_OK) return r;
+  }
+  if (fp32)
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(CELL_THREADS), 0, ctx->stream, ctx->q32, ctx->q,
+                       n);
   HIP_TRY(ctx, hipGetLastError());
   return HGKS_OK;
 }
@@ -1917,56 +2040,12 @@ hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q
   b->ws = static_cast<char*>(ws_dev);
   b->ws_bytes = ws_bytes;
   b->latched = HGKS_OK;
-  char* base = static_cast<char*>(ws_dev);
-  size_t off = 0;
-  std::vector<BatchEntry> host(n);
-  for (int i = 0; i < n; ++i) {
-    const size_t sz = align256(make_layout(cfgs[i]).total);
-    hgks_ctx m = nullptr;
-    hgks_status st = hgks_init(&cfgs[i], q_devs[i], base + off, sz, hip_stream, 0.0, &m);
-    if (st != HGKS_OK) {
-      b->err = "member " + std::to_string(i) + ": " + (m ? m->err : std::string("init failed"));
-      hgks_destroy(b);
-      return st;
-    }
-    b->members.push_back(m);
-    off += sz;
-    BatchEntry& e = host[i];
-    e.P = m->P;
-    e.q = m->q;
-    e.qs = m->qs;
-    e.acc = m->acc;
-    e.B = m->B;
-    for (int d = 0; d < 3; ++d) e.F[d] = m->F[d];
-    e.sc = m->sc;
-    e.qref = m->qref;
-    e.cfl = cfgs[i].cfl;
-  }
-  b->pre = batch_prefix(n, cfgs);
-  const std::vector<int> coarse = batch_coarse(n, b->pre, b->table.coarse_off);
-  BatchEntry* dE = reinterpret_cast<BatchEntry*>(base + off);
-  off += align256((size_t)n * sizeof(BatchEntry));
-  int* dpre = reinterpret_cast<int*>(base + off);
-  off += align256(b->pre.size() * sizeof(int));
-  int* dcoarse = reinterpret_cast<int*>(base + off);
-  HIP_TRY(b, hipMemcpyAsync(dE, host.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(b, hipMemcpyAsync(dpre, b->pre.data(), b->pre.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(b, hipMemcpyAsync(dcoarse, coarse.data(), coarse.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(b, hipStreamSynchronize(b->stream));
-  b->table.E = dE;
-  b->table.pre = dpre;
-  b->table.coarse = dcoarse;
-  b->table.n = n;
-  hgks_status st = batch_autotune(b);
+  const hgks_status st = batch_init_body(b, n, cfgs, q_devs, ws_dev, hip_stream);
   if (st != HGKS_OK) {
+    static_error("hgks_batch_init", b->err.c_str());
     hgks_destroy(b);
     return st;
   }
-  // capture one step
-  HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-  enqueue_batch_step(b);
-  HIP_TRY(b, hipStreamEndCapture(b->stream, &b->graph));
-  HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   *out = b;
   return HGKS_OK;
 }

@@ -284,6 +284,8 @@ class Solver:
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.q.device)
+        # the copies above ran on the current stream; the library's work on its own
+        self.stream.wait_stream(torch.cuda.current_stream(self.q.device))
         self.ctx = hgks_init(self.cfg, self.q.data_ptr(), self.ws_ptr, self.ws_bytes, self.stream.cuda_stream, t0)
 
     def step(self, nsteps: int = 1, dt_fixed: float = 0.0):
@@ -301,6 +303,7 @@ class Solver:
         qd = torch.as_tensor(q, dtype=torch.float64, device=self.q.device).contiguous()
         L = torch.empty_like(qd)
         dL = torch.empty_like(qd)
+        self.stream.wait_stream(torch.cuda.current_stream(self.q.device))
         hgks_residual(self.ctx, qd.data_ptr(), dt, L.data_ptr(), dL.data_ptr())
         return L, dL
 
