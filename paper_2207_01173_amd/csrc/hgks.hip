@@ -503,6 +503,24 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
+  // FP64: the equilibrium part's time coefficients and 1/(2 lambda0) are made
+  // in phase 1 and read only in phase 4.  They wait in LDS (one slot per
+  // lane) instead of occupying registers through the two side phases, where
+  // the compiler would otherwise spill them to scratch memory (16-60 bytes
+  // per lane; reloads wait on the vector-memory counter).  The empty asm with
+  // a memory clobber keeps the stores and the reloads apart, so the values
+  // really leave the registers.
+  constexpr bool kCarry = sizeof(R) == 8;
+  __shared__ double carry_lds[kCarry ? 7 : 1][kCarry ? FLUX_THREADS : 1];
+  if constexpr (kCarry) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      carry_lds[i][tid] = acc.Cn[i];
+      carry_lds[3 + i][tid] = acc.Cd[i];
+    }
+    carry_lds[6][tid] = acc.ihl0;
+    asm volatile("" ::: "memory");
+  }
 
   // phase 2: left side
   {
@@ -544,6 +562,15 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     for (int k = 0; k < 5; ++k) {
       stencil(b_d0(k), pa[k]);
       dq0n[k] = gauss_linear(pa[k], gp) * sn;
+    }
+    if constexpr (kCarry) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        acc.Cn[i] = carry_lds[i][tid];
+        acc.Cd[i] = carry_lds[3 + i][tid];
+      }
+      acc.ihl0 = carry_lds[6][tid];
     }
     flux_finish(dq0n, g, acc, Fn, Fd);
   }

@@ -461,6 +461,25 @@ __device__ __forceinline__ R thermal(const R v[5], R U, R V, R W, R hu2) {
   return v[4] - (U * v[1] + V * v[2] + W * v[3]) + hu2 * v[0];
 }
 
+// thermal() of a u^0 moment <G psi> of a u-series G = sum_i u^i g_i (quads of
+// the g_i, u-table Mu), without forming the moment vector:
+//   sum_i [ e0_i Tw_i + Mu[i] (er_i / 2 - V ev_i - W ew_i) ],
+// Tw_i = Mu[i+2]/2 - U Mu[i+1] + hu2 Mu[i] the weights (thermal_weights) that
+// the energy, momentum and density rows of the moment give u^i in the frame
+// of (U, V, W).
+template <class R>
+__device__ __forceinline__ void thermal_weights(const R Mu[7], R U, R hu2, R Tw[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Tw[i] = R(0.5) * Mu[i + 2] - U * Mu[i + 1] + hu2 * Mu[i];
+}
+template <class R, int NS>
+__device__ __forceinline__ R thermal_series(const Quad<R> q[NS], const R Mu[7], const R Tw[4], R V, R W) {
+  R t = R(0);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) t += q[i].e0 * Tw[i] + Mu[i] * (R(0.5) * q[i].er - V * q[i].ev - W * q[i].ew);
+  return t;
+}
+
 // Running state of one Gauss-point flux evaluation, filled in phases so that
 // the caller can reconstruct the left inputs, consume them, then the right
 // ones, keeping few values live at a time.
@@ -560,13 +579,11 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
     }
   }
   {
-    R Y[5];
-    assemble<R, 0, 1>(unit, Mh, Y);
-    const R y1 = thermal(Y, U0, V0, W0, Acc.hu2);
-    assemble<R, 0, 4>(pi, Mh, Y);
-    const R y2 = thermal(Y, U0, V0, W0, Acc.hu2);
-    assemble<R, 0, 3>(qa, Mh, Y);
-    const R y3 = thermal(Y, U0, V0, W0, Acc.hu2);
+    R Tw[4];
+    thermal_weights(Mh, U0, Acc.hu2, Tw);
+    const R y1 = thermal_series<R, 1>(unit, Mh, Tw, V0, W0);
+    const R y2 = thermal_series<R, 4>(pi, Mh, Tw, V0, W0);
+    const R y3 = thermal_series<R, 3>(qa, Mh, Tw, V0, W0);
     Acc.wn += rho * (Acc.Cn[3] * y1 + Acc.Cn[4] * y2 + Acc.Cn[5] * y3);
     Acc.wd += rho * (Acc.Cd[3] * y1 + Acc.Cd[4] * y2 + Acc.Cd[5] * y3);
   }
@@ -631,12 +648,11 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
     Fn[k] = Acc.Fn[k] + rho * (Acc.Cn[0] * X1[k] + Acc.Cn[1] * X2[k] + Acc.Cn[2] * X3[k]);
     Fd[k] = Acc.Fd[k] + rho * (Acc.Cd[0] * X1[k] + Acc.Cd[1] * X2[k] + Acc.Cd[2] * X3[k]);
   }
-  R Y[5];
-  assemble<R, 0, 1>(unit, Mf, Y);
-  const R y1 = thermal(Y, s0.U, s0.V, s0.W, Acc.hu2);
+  R Tw[4];
+  thermal_weights(Mf, s0.U, Acc.hu2, Tw);
+  const R y1 = thermal_series<R, 1>(unit, Mf, Tw, s0.V, s0.W);
   const R y2 = thermal(T, s0.U, s0.V, s0.W, Acc.hu2);
-  assemble<R, 0, 3>(qa, Mf, Y);
-  const R y3 = thermal(Y, s0.U, s0.V, s0.W, Acc.hu2);
+  const R y3 = thermal_series<R, 3>(qa, Mf, Tw, s0.V, s0.W);
   const R wn = Acc.wn + rho * (Acc.Cn[0] * y1 + Acc.Cn[1] * y2 + Acc.Cn[2] * y3);
   const R wd = Acc.wd + rho * (Acc.Cd[0] * y1 + Acc.Cd[1] * y2 + Acc.Cd[2] * y3);
   // the heat flux is linear in the window, so the correction applies to F^n
