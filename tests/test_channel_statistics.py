@@ -1,5 +1,5 @@
-"""The channel statistics of bench.py on a manufactured field with closed-form
-answers (CPU, torch)."""
+"""The channel statistics (paper_2207_01173_amd.channel) on a manufactured
+field with closed-form answers (CPU, torch)."""
 import math
 
 import numpy as np
@@ -10,7 +10,7 @@ from paper_2207_01173_amd import workloads as W
 
 def test_channel_statistics_manufactured_field():
     torch = pytest.importorskip("torch")
-    import bench
+    from paper_2207_01173_amd.channel import channel_statistics
 
     p = W.channel_params((16, 12, 8), ma_b=0.5, re_b=3000.0, y_stretch=0.0)
     nx, ny, nz = p["n"]
@@ -25,7 +25,7 @@ def test_channel_statistics_manufactured_field():
     Wv = np.zeros_like(U)
     rho = np.full_like(U, rho0)
     q = torch.as_tensor(np.ascontiguousarray(W.conserved(rho, U, V, Wv, rho0 * T0, p["gamma"])))
-    st = bench.channel_statistics(q, p, y)
+    st = channel_statistics(q, p, y)
     half = len(st["y"])
     assert half == ny // 2
     np.testing.assert_allclose(st["u_rms"], a / math.sqrt(2.0), rtol=1e-12)
