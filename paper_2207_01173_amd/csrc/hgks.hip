@@ -171,6 +171,20 @@ template <class R> constexpr bool B_INTERLEAVED = sizeof(R) == 8;
 template <class R> __host__ __device__ constexpr size_t b_pos(size_t i, int g, size_t NB) {
   return B_INTERLEAVED<R> ? 2 * i + g : (size_t)g * NB + i;
 }
+// FP64 face data are tile-major: for each 16-face run along x of a row
+// (z, y) of B, the 35 quantities' two Gauss lines sit together in one chunk
+// of 35 x 32 doubles (8960 bytes), quantity q at 32 q, face x at 2 (x mod 16)
+// + line.  A flux wave's loads of one stencil row then touch one chunk (the
+// ten quantities of a phase: 2.5 KB contiguous) instead of 35 runs of 256
+// bytes spread over 35 quantity planes, and a reconstruction wave's stores
+// fill chunks.  FP32 face data keep quantity planes.
+constexpr int B_CHUNK = B_COUNT * 32;  // doubles per (row, 16-face run)
+// Index of quantity 0, line 0 of face (x, y, z) (B coordinates) in FP64 B,
+// for row pitch bp (a multiple of 32) and be1 rows per z plane.
+__host__ __device__ inline size_t b64_face(int x, int y, int z, int bp, int be1) {
+  return (((size_t)z * be1 + y) * (size_t)(bp >> 4) + (size_t)(x >> 4)) * B_CHUNK + 2 * (size_t)(x & 15);
+}
+
 // Byte distance between a quantity of B and the next one (2 NB entries).
 template <class R> __host__ __device__ inline uint32_t second_pair_offset(size_t NB) {
   return (uint32_t)(2 * NB * sizeof(R));
@@ -318,12 +332,14 @@ __device__ __forceinline__ void recon_tile(const ST* __restrict__ q, const Param
         ((size_t)(f[2] - bo[2]) * be[1] + (f[1] - bo[1])) * face_pitch(be[0]) + (f[0] - bo[0]);
     // B is written once and read once, by the flux kernel: non-temporal stores
     // (no L2 allocation for a stream many times the cache's size).
-    HGKS_GLOBAL R* out = gmem(B) + b_pos<R>(bidx, 0, NB);
+    HGKS_GLOBAL R* out =
+        gmem(B) + (B_INTERLEAVED<R> ? b64_face(f[0] - bo[0], f[1] - bo[1], f[2] - bo[2], face_pitch(be[0]), be[1])
+                                    : b_pos<R>(bidx, 0, NB));
     using R2 = R __attribute__((ext_vector_type(2)));
     auto put = [&](int q, const R val[2]) {
       if constexpr (B_INTERLEAVED<R>) {
         const R2 v2 = {val[0], val[1]};
-        __builtin_nontemporal_store(v2, reinterpret_cast<HGKS_GLOBAL R2*>(&out[q * qstride]));
+        __builtin_nontemporal_store(v2, reinterpret_cast<HGKS_GLOBAL R2*>(&out[q * 32]));
       } else {
         __builtin_nontemporal_store(val[0], &out[q * qstride]);
         __builtin_nontemporal_store(val[1], &out[q * qstride + NB]);
@@ -416,28 +432,42 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   const int bp = face_pitch(be[0]);
   const size_t NB = (size_t)bp * be[1] * be[2];
   const size_t qstride = 2 * NB;
-  // Addressing of B: every face of a block lies in one z plane of B for each
-  // stencil row j (z is the normal for y and z faces, and t2 for x faces,
-  // whose z then depends on j only), so a load is a block-uniform base (the
-  // quantity's start plus that plane's offset, held in scalar registers) plus
-  // a 32-bit lane offset within the plane: the position of the lane's face
-  // and Gauss line, and for the Gauss-point pairs the partner quantity's
-  // plane (one quantity further: the lane offsets stay below 2^32, checked
-  // when the configuration is validated).
+  // Addressing of B: a load is a wave-uniform base held in scalar registers
+  // plus a 32-bit lane offset.  FP64 (tile-major): the base is quantity qi's
+  // place in the row (z, y) of the stencil row j, the lane offset the face's
+  // 16-face chunk and place in it, and for the Gauss-point pairs the partner
+  // quantity (one quantity, 32 doubles, further).  FP32 (quantity planes):
+  // every face of a block lies in one z plane of B for each stencil row j (z
+  // is the normal for y and z faces, and t2 for x faces, whose z then depends
+  // on j only), so the base is the quantity's start plus that plane's
+  // offset and the lane offset the face's place in the plane, plus the
+  // partner quantity's plane for the pairs (the lane offsets stay below
+  // 2^32, checked when the configuration is validated).
   const size_t plane = (size_t)bp * be[1];
-  const uint32_t pair_off = second_pair_offset<R>(NB);
+  // FP64 (tile-major B): the next quantity is 32 doubles further, the base of
+  // a stencil row is its (z, y) row of chunks (wave-uniform: one y per wave),
+  // the lane offset the face's chunk and place in it.
+  constexpr bool kTile = B_INTERLEAVED<R>;
+  const uint32_t pair_off = kTile ? 32u * sizeof(R) : second_pair_offset<R>(NB);
+  const size_t qbytes = kTile ? 32 * sizeof(R) : qstride * sizeof(R);
   const bool second = g2 != 0;
   uint32_t off[5];     // lane offsets, pair partner included on the g2 = 1 lanes
-  size_t zoff[5];      // byte offsets of the stencil rows' z planes (block-uniform)
+  size_t zoff[5];      // byte offsets of the stencil rows (block-uniform z plane; FP64: wave-uniform row)
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     int b[3] = {f[0], f[1], f[2]};
     int t = f[D2] + j - 2;
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
-    zoff[j] = sizeof(R) * b_pos<R>((size_t)(b[2] - bo[2]) * plane, 0, NB);
-    const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
-    off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
+    if constexpr (kTile) {
+      zoff[j] = sizeof(R) * b64_face(0, b[1] - bo[1], b[2] - bo[2], bp, be[1]);
+      off[j] = (uint32_t)sizeof(R) * (uint32_t)(b64_face(b[0] - bo[0], 0, 0, bp, be[1]) + g1) +
+               (second ? pair_off : 0u);
+    } else {
+      zoff[j] = sizeof(R) * b_pos<R>((size_t)(b[2] - bo[2]) * plane, 0, NB);
+      const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
+      off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
+    }
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
@@ -460,9 +490,9 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.iT_ref = R(P.iT_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
-  // Block-uniform base of quantity qi and stencil row j.
+  // Wave-uniform base of quantity qi and stencil row j.
   auto row_base = [&](int qi, int j) {
-    return uniform_ptr(reinterpret_cast<const HGKS_GLOBAL char*>(Bg + (size_t)qi * qstride) + zoff[j]);
+    return uniform_ptr(reinterpret_cast<const HGKS_GLOBAL char*>(Bg) + (size_t)qi * qbytes + zoff[j]);
   };
   // Five stencil values of quantity qi along t2 (qi the same on every lane).
   auto stencil = [&](int qi, R v[5]) {
