@@ -379,6 +379,22 @@ __global__ __launch_bounds__(RECON_THREADS) void recon_kernel(const ST* __restri
   recon_tile<DIR, R, ST>(q, P, qref, B, xcd_linear_block(recon_tiles<DIR, R>(P)), A);
 }
 
+// Asynchronous copy of 16 bytes per lane from global memory into LDS (lane l's
+// bytes land at lds + 16 l; lds must be the same on every lane of the wave).
+// Completion is tracked by the wave's vector-memory counter.
+__device__ __forceinline__ void dma16_to_lds(const HGKS_GLOBAL char* src, double* lds) {
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const HGKS_GLOBAL void*>(src),
+                                   (__attribute__((address_space(3))) void*)(lds), 16, 0, 0);
+}
+// Every outstanding vector-memory operation of the wave complete (the LDS
+// copies above included); the compiler moves no memory access across it.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// The value counts as defined by this (empty) asm: no wait for the load that
+// produced it is left to the compiler after this point (the vector-memory
+// counter retires in order, so such a wait would also wait for every copy
+// issued after the load).
+template <class T> __device__ __forceinline__ void produced_here(T& x) { asm volatile("" : "+v"(x)); }
+
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
 // At least two blocks (two waves per SIMD) resident per CU: the FP64 kernel is
 // held to 256 registers per lane, spilling a few phase-1 values that only
@@ -403,6 +419,171 @@ template <int TX> __host__ __device__ inline int flux_tiles(const Params& P, int
 // flux tile `lin` of direction DIR.  Lane layout in a wavefront: lanes
 // 16 g .. 16 g + 15 hold Gauss point g of 16 consecutive faces along x; the
 // four waves of the block take four 16-face groups of the TX x (64/TX) tile.
+// The flux of one lane's Gauss point and the face's 2x2 Gauss sum (the phases
+// of flux_tile below, with the stencils from a caller-given source), for the
+// staged tiles of flux_tile4.  The source: begin(p) at the start of phase p (0..3), pair(qi0, v)
+// the five stencil values of quantity qi0 + g2 (Gauss-point pairs: see below),
+// plain(qi, v) those of quantity qi.  f is the lane's face (clamped to a real
+// one for the lanes beyond the grid, valid false), sn, st1, st2 the metric
+// factors of its normal slope and of its Gauss point's tangential slopes,
+// rl the reference state (local frame) added back to the reconstructed
+// deviations; NT threads per block.
+template <int DIR, class R, int NT, bool kCarryLent, class Begin, class Pair, class Plain>
+__device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& plain, const Params& P, double dt,
+                                          double* __restrict__ F, const int f[3], bool valid, int gpi, R sn, R st1,
+                                          R st2, const double rl[5], double* carry_area) {
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  const int tid = threadIdx.x;
+  const int g2 = gpi & 1;
+  const bool second = g2 != 0;
+  int fe[3];
+  face_extents(P, DIR, fe);
+  GaussPoint<R> gp(g2);
+  GasParams<R> g;
+  g.gm1 = R(P.gm1);
+  g.K = R(P.K);
+  g.K3 = R(P.K + 3.0);
+  g.iK3 = R(P.iK3);
+  g.mu_ref = R(P.mu_ref);
+  g.iT_ref = R(P.iT_ref);
+  g.mu_exp = R(P.mu_exp);
+  g.pr_fix = R(P.pr_fix);
+  // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
+  // lane ^ 16) share every t2 stencil.  Each reconstructs one of two
+  // quantities at both points (its own and the mirrored one) and swaps the
+  // mirrored result with its partner.  The g2 = 0 lane takes quantity qi0
+  // (Q^l, the normal slopes), the g2 = 1 lane the next one (Q^r, the t1
+  // slopes).
+  auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
+
+  R pa[5][5];
+
+  // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
+  R ql[5], qr[5], tl2[5], tr2[5];
+  begin(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R v[5], val, der, val_m, der_m;
+    pair(b_ql(k), v);
+    gauss_value_slope_mirror(v, gp, val, der, val_m, der_m);
+    const R ov = partner(val_m), od = partner(der_m);  // the other state at this lane's point
+    ql[k] = R(double(second ? ov : val) + rl[k]);
+    tl2[k] = (second ? od : der) * st2;
+    qr[k] = R(double(second ? val : ov) + rl[k]);
+    tr2[k] = (second ? der : od) * st2;
+  }
+  FluxAcc<R> acc;
+  flux_begin(ql, qr, g, R(dt), acc);
+  // FP64: the equilibrium part's time coefficients and 1/(2 lambda0) are made
+  // in phase 1 and read only in phase 4.  They wait in LDS (one slot per
+  // lane) instead of occupying registers through the two side phases, where
+  // the compiler would otherwise spill them to scratch memory (16-60 bytes
+  // per lane; reloads wait on the vector-memory counter).  The empty asm with
+  // a memory clobber keeps the stores and the reloads apart, so the values
+  // really leave the registers.
+  // The caller may lend LDS for them (kCarryLent: carry_area, 7 NT doubles
+  // free from the start of phase 2 on).
+  constexpr bool kCarry = sizeof(R) == 8;
+  __shared__ double carry_own[kCarry && !kCarryLent ? 7 * NT : 1];
+  double* const carry_lds = kCarryLent ? carry_area : carry_own;
+  begin(1);
+  if constexpr (kCarry) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      carry_lds[i * NT + tid] = acc.Cn[i];
+      carry_lds[(3 + i) * NT + tid] = acc.Cd[i];
+    }
+    carry_lds[6 * NT + tid] = acc.ihl0;
+    asm volatile("" ::: "memory");
+  }
+
+  // phase 2: left side
+  {
+    R dq[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      pair(b_dln(k), pa[k]);
+      R val, val_m;
+      gauss_value_mirror(pa[k], gp, val, val_m);
+      const R o = partner(val_m);
+      dq[0][k] = (second ? o : val) * sn;
+      dq[1][k] = (second ? val : o) * st1;
+      dq[2][k] = tl2[k];
+    }
+    flux_side<R, true>(ql, dq, g, acc);
+  }
+
+  // phase 3: right side
+  {
+    R dq[3][5];
+    begin(2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      pair(b_drn(k), pa[k]);
+      R val, val_m;
+      gauss_value_mirror(pa[k], gp, val, val_m);
+      const R o = partner(val_m);
+      dq[0][k] = (second ? o : val) * sn;
+      dq[1][k] = (second ? val : o) * st1;
+      dq[2][k] = tr2[k];
+    }
+    flux_side<R, false>(qr, dq, g, acc);
+  }
+
+  // phase 4: equilibrium part and Prandtl correction
+  R Fn[5], Fd[5];  // F^n and dF^n/dt at this lane's Gauss point
+  {
+    R dq0n[5];
+    begin(3);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      plain(b_d0(k), pa[k]);
+      dq0n[k] = gauss_linear(pa[k], gp) * sn;
+    }
+    if constexpr (kCarry) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        acc.Cn[i] = carry_lds[i * NT + tid];
+        acc.Cd[i] = carry_lds[(3 + i) * NT + tid];
+      }
+      acc.ihl0 = carry_lds[6 * NT + tid];
+    }
+    flux_finish(dq0n, g, acc, Fn, Fd);
+  }
+
+  // ---- 2x2 Gauss sum across the four lanes of the face -------------------
+  double sn5[5], sd5[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    sn5[k] = double(Fn[k]);
+    sd5[k] = double(Fd[k]);
+    sn5[k] += __shfl_xor(sn5[k], 16);
+    sd5[k] += __shfl_xor(sd5[k], 16);
+    sn5[k] += __shfl_xor(sn5[k], 32);
+    sd5[k] += __shfl_xor(sd5[k], 32);
+  }
+  if (!valid || gpi != 0) return;  // this lane only
+  const double qarea = 0.25 * gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
+  double loc[10];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    loc[k] = qarea * sn5[k];
+    loc[5 + k] = qarea * sd5[k];
+  }
+  const int fpitch = face_pitch(fe[0]);
+  const size_t NF = (size_t)fpitch * fe[1] * fe[2];
+  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fpitch + f[0];
+  // rotate momentum back to the global frame
+  const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
+  HGKS_GLOBAL double* Fg = gmem(F);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    Fg[gcomp[k] * NF + fi] = loc[k];
+    Fg[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
+  }
+}
+
 template <int DIR, class R, int TX>
 __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params& P, const double* __restrict__ qref,
                                           double dt, double* __restrict__ F, int lin) {
@@ -635,6 +816,125 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     Fg[gcomp[k] * NF + fi] = loc[k];
     Fg[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
   }
+}
+
+// ---- FP64 flux tiles with the t2 stencil rows shared in LDS (x and z faces) --
+// For x and z faces t2 is z or y.  A flux block takes 16 faces along x at 4
+// consecutive t2 positions (256 threads: wave w holds position w), so it
+// needs 8 rows of B per quantity instead of 4 x 5.  At its start the block
+// copies all 35 quantities of those rows into LDS (asynchronous global -> LDS
+// loads, 16 bytes per lane: one face's two Gauss lines; 70 KB), then every
+// phase reads its stencils from there; the other block on the CU computes
+// meanwhile.  y faces keep flux_tile: their t2 is x, whose five stencil rows
+// are shifts of the run of faces that a wave already reads together.
+constexpr int FLUX4_X = 16, FLUX4_P = 4, FLUX4_ROWS = FLUX4_P + 4;
+__host__ __device__ inline void flux4_tile_counts(const Params& P, int d, int nt[3]) {
+  int fe[3];
+  face_extents(P, d, fe);
+  const int d2 = (d + 2) % 3;
+  for (int a = 0; a < 3; ++a) nt[a] = fe[a];
+  nt[0] = (fe[0] + FLUX4_X - 1) / FLUX4_X;
+  nt[d2] = (fe[d2] + FLUX4_P - 1) / FLUX4_P;
+}
+__host__ __device__ inline int flux4_tiles(const Params& P, int d) {
+  int nt[3];
+  flux4_tile_counts(P, d, nt);
+  return nt[0] * nt[1] * nt[2];
+}
+
+template <int DIR>
+__device__ __forceinline__ void flux_tile4(const double* __restrict__ B, const Params& P,
+                                           const double* __restrict__ qref, double dt, double* __restrict__ F,
+                                           int lin) {
+  static_assert(DIR != 1, "y faces use flux_tile");
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  constexpr int DO = DIR == 0 ? 1 : 2;  // the axis that is neither x nor t2: one row per block
+  int fe[3], be[3], bo[3];
+  face_extents(P, DIR, fe);
+  b_extents(P, DIR, be, bo);
+  int nt[3], tc[3];
+  flux4_tile_counts(P, DIR, nt);
+  tile_coords(lin, nt, D2, tc);  // t2 tiles adjacent: consecutive blocks share four staged rows
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int f[3];
+  f[0] = tc[0] * FLUX4_X + (lane & 15);
+  f[D2] = tc[D2] * FLUX4_P + w;
+  f[DO] = tc[DO];
+  const int gpi = (lane >> 4) & 3;
+  const int g1 = gpi >> 1, g2 = gpi & 1;
+  const bool valid = f[0] < fe[0] && f[D2] < fe[D2];
+  if (!valid) {  // keep the lane for the shuffles, on a real face
+    f[0] = min(f[0], fe[0] - 1);
+    f[D2] = min(f[D2], fe[D2] - 1);
+  }
+
+  // Staged rows: [quantity][row][face] of 16-byte entries, row r holding
+  // t2 = first position - 2 + r (wrapped on a periodic axis; on a wall axis
+  // clamped to the last ghost row, which only lanes past the grid's end
+  // read).  Entry e = (q FLUX4_ROWS + r) FLUX4_X + face; thread tid copies
+  // entries tid + 256 k, so each wave's copy lands in 64 consecutive entries.
+  // Row and face of those entries do not depend on k and the quantity is
+  // 2 k + tid / 128, so one lane address serves every copy: the k-th is 2 k
+  // quantities (512 bytes) further.
+  __shared__ double2 stage[B_COUNT][FLUX4_ROWS][FLUX4_X];
+  constexpr int kEntries = B_COUNT * FLUX4_ROWS * FLUX4_X;
+  {
+    const int r = (tid >> 4) & (FLUX4_ROWS - 1), fi = tid & (FLUX4_X - 1);
+    int t = tc[D2] * FLUX4_P - 2 + r;
+    if (P.bc[D2] == HGKS_BC_ISOTHERMAL_WALL) t = min(t, P.n[D2] + 1);
+    else t = ((t % P.n[D2]) + P.n[D2]) % P.n[D2];
+    int b[3];
+    b[0] = min(tc[0] * FLUX4_X + fi, fe[0] - 1);
+    b[D2] = t;
+    b[DO] = f[DO];
+    const HGKS_GLOBAL char* lane_src =
+        reinterpret_cast<const HGKS_GLOBAL char*>(gmem(B)) +
+        (b64_face(b[0] - bo[0], b[1] - bo[1], b[2] - bo[2], face_pitch(be[0]), be[1]) + (size_t)(tid >> 7) * 32) *
+            sizeof(double);
+#pragma unroll
+    for (int k = 0; k < (kEntries + FLUX_THREADS - 1) / FLUX_THREADS; ++k)
+      if (FLUX_THREADS * k + 64 * w < kEntries)  // wave-uniform
+        dma16_to_lds(lane_src + (size_t)(2 * k) * 32 * sizeof(double),
+                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * w));
+  }
+  double sn = gmem(P.dface[DIR])[f[DIR]];
+  double st1 = gmem(P.dgp[D1])[2 * f[D1] + g1];
+  double st2 = gmem(P.dgp[D2])[2 * f[D2] + g2];
+  const HGKS_GLOBAL double* qrg = gmem(qref);
+  double rl[5];
+  rl[0] = qrg[0];
+  rl[1] = qrg[1 + DIR];
+  rl[2] = qrg[1 + D1];
+  rl[3] = qrg[1 + D2];
+  rl[4] = qrg[4];
+  wait_vmem();      // this wave's copies and loads have landed
+  __syncthreads();  // and every wave's
+  const double* const st = reinterpret_cast<const double*>(&stage[0][0][0]);
+  const int base = (w * FLUX4_X + (lane & 15)) * 2 + g1;  // quantity 0, row w (stencil row 0), line g1
+  auto begin = [&](int p) {
+    // phase 1's quantities are read by then; their space takes the carried values
+    if (p == 1) __syncthreads();
+  };
+  auto pair = [&](int qi0, double v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = st[base + ((qi0 + g2) * FLUX4_ROWS + j) * FLUX4_X * 2];
+  };
+  auto plain = [&](int qi, double v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = st[base + (qi * FLUX4_ROWS + j) * FLUX4_X * 2];
+  };
+  flux_lane<DIR, double, FLUX_THREADS, true>(begin, pair, plain, P, dt, F, f, valid, gpi, sn, st1, st2, rl,
+                                             reinterpret_cast<double*>(&stage[0][0][0]));
+}
+
+template <int DIR>
+__global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux4_kernel(const double* __restrict__ B, Params P,
+                                                                             const double* __restrict__ qref,
+                                                                             const Scalars* __restrict__ sc,
+                                                                             int use_residual_dt,
+                                                                             double* __restrict__ F) {
+  const double dt = use_residual_dt ? sc->dt_residual : sc->dt;
+  flux_tile4<DIR>(B, P, qref, dt, F, xcd_linear_block(flux4_tiles(P, DIR)));
 }
 
 template <int DIR, class R>
@@ -1008,7 +1308,10 @@ __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_batch_kern
   if (t >= t1) return;
   int local;
   const BatchEntry& e = T.E[find_instance(T, flux_row<TX>(DIR), t, local)];
-  flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
+  if constexpr (sizeof(R) == 8 && DIR != 1)  // the tiles of a standalone run of the member
+    flux_tile4<DIR>(static_cast<const double*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
+  else
+    flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
 }
 
 template <int STAGE>
@@ -1357,6 +1660,20 @@ static hgks_status validate(const hgks_config* c, const char** why) {
     }                                                                                    \
   } while (0)
 
+// The flux launch of direction D: FP64 x and z faces in blocks of 16 faces at
+// 4 t2 positions (flux4_kernel), the others in blocks of 64 faces of one t2
+// position (flux_kernel).
+template <int D, class R>
+static void launch_flux(const Params& P, hipStream_t stream, const R* B, const double* qref, const Scalars* sc,
+                        int use_residual_dt, double* F) {
+  if constexpr (sizeof(R) == 8 && D != 1)
+    hipLaunchKernelGGL((flux4_kernel<D>), dim3((unsigned)flux4_tiles(P, D)), dim3(FLUX_THREADS), 0, stream, B, P,
+                       qref, sc, use_residual_dt, F);
+  else
+    hipLaunchKernelGGL((flux_kernel<D, R>), dim3((unsigned)flux_tiles<16>(P, D)), dim3(FLUX_THREADS), 0, stream, B,
+                       P, qref, sc, use_residual_dt, F);
+}
+
 // Reconstruction and flux of the three directions of one stage on `stream`
 // (faces of qin -> F[d]); hook(cls) / hook(-1) bracket each launch (the
 // context's profiling events; a no-op elsewhere).
@@ -1366,7 +1683,6 @@ static hipError_t enqueue_fluxes(const Params& P, hipStream_t stream, const S* q
   auto recon_blocks = [&](int d) {
     return (unsigned)(d == 0 ? recon_tiles<0, R>(P) : (d == 1 ? recon_tiles<1, R>(P) : recon_tiles<2, R>(P)));
   };
-  auto flux_blocks = [&](int d) { return (unsigned)flux_tiles<16>(P, d); };
   hipError_t e;
 #define HGKS_DIRECTION(D)                                                                                    \
   if ((e = hook(PROF_RECON)) != hipSuccess) return e;                                                        \
@@ -1374,8 +1690,7 @@ static hipError_t enqueue_fluxes(const Params& P, hipStream_t stream, const S* q
                      qref, B);                                                                               \
   if ((e = hook(-1)) != hipSuccess) return e;                                                                \
   if ((e = hook(PROF_FLUX)) != hipSuccess) return e;                                                         \
-  hipLaunchKernelGGL((flux_kernel<D, R>), dim3(flux_blocks(D)), dim3(FLUX_THREADS), 0, stream, B, P, qref,  \
-                     sc, use_residual_dt, F[D]);                                                             \
+  launch_flux<D, R>(P, stream, B, qref, sc, use_residual_dt, F[D]);                                          \
   if ((e = hook(-1)) != hipSuccess) return e;
   HGKS_DIRECTION(0)
   HGKS_DIRECTION(1)
@@ -1487,8 +1802,10 @@ static std::vector<int> batch_prefix(int n, const hgks_config* cfgs) {
     items[PRE_RECON + 1] = f32 ? recon_tiles<1, float>(P) : recon_tiles<1, double>(P);
     items[PRE_RECON + 2] = f32 ? recon_tiles<2, float>(P) : recon_tiles<2, double>(P);
     for (int d = 0; d < 3; ++d) {
-      items[flux_row<16>(d)] = flux_tiles<16>(P, d);
-      items[flux_row<32>(d)] = flux_tiles<32>(P, d);
+      // FP64 x and z faces: the 4-position tiles whatever the width
+      const bool four = !f32 && d != 1;
+      items[flux_row<16>(d)] = four ? flux4_tiles(P, d) : flux_tiles<16>(P, d);
+      items[flux_row<32>(d)] = four ? flux4_tiles(P, d) : flux_tiles<32>(P, d);
     }
     items[PRE_CELL] = (long long)((cells(P) + CELL_THREADS - 1) / CELL_THREADS);
     for (int r = 0; r < PRE_ROWS; ++r) {
