@@ -395,6 +395,91 @@ __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" 
 // issued after the load).
 template <class T> __device__ __forceinline__ void produced_here(T& x) { asm volatile("" : "+v"(x)); }
 
+// Lane exchanges between the rows of a wavefront (row = 16 lanes), on the
+// VALU (gfx950 permlane swaps), every lane active.  swap_rows16(x, y): on an
+// even row x keeps its value and y takes the x of the odd row above it; on
+// an odd row y keeps its value and x takes the y of the even row below it.
+// swap_rows32(x, y): the same between the half-waves (rows 0-1 and 2-3): x
+// of the upper half takes y of the lower half, y of the lower half takes x
+// of the upper half.
+template <bool kHalf> __device__ __forceinline__ void swap_rows_u32(uint32_t& x, uint32_t& y) {
+  if constexpr (kHalf) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  }
+}
+template <bool kHalf> __device__ __forceinline__ void swap_rows(float& x, float& y) {
+  uint32_t a = __float_as_uint(x), b = __float_as_uint(y);
+  swap_rows_u32<kHalf>(a, b);
+  x = __uint_as_float(a);
+  y = __uint_as_float(b);
+}
+template <bool kHalf> __device__ __forceinline__ void swap_rows(double& x, double& y) {
+  const uint64_t a = (uint64_t)__double_as_longlong(x), b = (uint64_t)__double_as_longlong(y);
+  uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+  swap_rows_u32<kHalf>(al, bl);
+  swap_rows_u32<kHalf>(ah, bh);
+  x = __longlong_as_double((long long)(((uint64_t)ah << 32) | al));
+  y = __longlong_as_double((long long)(((uint64_t)bh << 32) | bl));
+}
+template <class T> __device__ __forceinline__ void swap_rows16(T& x, T& y) { swap_rows<false>(x, y); }
+template <class T> __device__ __forceinline__ void swap_rows32(T& x, T& y) { swap_rows<true>(x, y); }
+
+// The face's 2x2 Gauss sum and its store.  Rows 0..3 of a wavefront hold the
+// Gauss points (g1, g2) = (row >> 1, row & 1) of the same 16 faces; Fn, Fd
+// are F^n and dF^n/dt at the lane's point (local frame).  Row pairs (0,1),
+// (2,3) are summed first, then the half-waves, each value in the order
+// (r0 + r1) + (r2 + r3).  Every sum ends on one row: rows 0..3 store F^n and
+// dF^n/dt of components (0, 1) (t[0]), (2, 3) (t[1]), and rows 0, 1 those of
+// component 4, each scaled by the quarter face area and rotated to the
+// global frame.
+template <int DIR, class R>
+__device__ __forceinline__ void gauss_sum_store(const Params& P, double* __restrict__ F, const int f[3], bool valid,
+                                                int gpi, const R Fn[5], const R Fd[5]) {
+  constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
+  double s[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double x = double(Fn[k]), y = double(Fd[k]);
+    swap_rows16(x, y);
+    s[k] = x + y;  // rows 0, 2: F^n over the row pair; rows 1, 3: dF^n/dt
+  }
+  double t[3];
+  {
+    double x = s[0], y = s[1];
+    swap_rows32(x, y);
+    t[0] = x + y;
+  }
+  {
+    double x = s[2], y = s[3];
+    swap_rows32(x, y);
+    t[1] = x + y;
+  }
+  {
+    double x = s[4], y = s[4];
+    swap_rows32(x, y);
+    t[2] = x + y;
+  }
+  if (!valid) return;
+  int fe[3];
+  face_extents(P, DIR, fe);
+  const double qarea = 0.25 * gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
+  const int fpitch = face_pitch(fe[0]);
+  const size_t NF = (size_t)fpitch * fe[1] * fe[2];
+  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fpitch + f[0];
+  const int fd = (gpi & 1) * 5, hi = gpi >> 1;
+  HGKS_GLOBAL double* Fg = gmem(F) + fi;
+  // global component of local components 0/1, 2/3 (momentum rotated back)
+  Fg[(fd + (hi ? 1 + DIR : 0)) * NF] = qarea * t[0];
+  Fg[(fd + (hi ? 1 + D2 : 1 + D1)) * NF] = qarea * t[1];
+  if (!hi) Fg[(fd + 4) * NF] = qarea * t[2];
+}
+
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
 // At least two blocks (two waves per SIMD) resident per CU: the FP64 kernel is
 // held to 256 registers per lane, spilling a few phase-1 values that only
@@ -434,11 +519,7 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
                                           R st2, const double rl[5], double* carry_area) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
   const int tid = threadIdx.x;
-  const int g2 = gpi & 1;
-  const bool second = g2 != 0;
-  int fe[3];
-  face_extents(P, DIR, fe);
-  GaussPoint<R> gp(g2);
+  GaussPoint<R> gp(gpi & 1);
   GasParams<R> g;
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
@@ -449,13 +530,11 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
   // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
-  // lane ^ 16) share every t2 stencil.  Each reconstructs one of two
-  // quantities at both points (its own and the mirrored one) and swaps the
-  // mirrored result with its partner.  The g2 = 0 lane takes quantity qi0
-  // (Q^l, the normal slopes), the g2 = 1 lane the next one (Q^r, the t1
-  // slopes).
-  auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
-
+  // lane ^ 16, an even row and the odd row above it) share every t2
+  // stencil.  Each reconstructs one of two quantities at both points and the
+  // pair exchanges the other point's values (swap_rows16).  The g2 = 0 lane
+  // takes quantity qi0 (Q^l, the normal slopes), the g2 = 1 lane the next
+  // one (Q^r, the t1 slopes).
   R pa[5][5];
 
   // phase 1: left/right values and their t2 slopes; equilibrium, tau, time integrals
@@ -463,14 +542,15 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
   begin(0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    R v[5], val, der, val_m, der_m;
+    R v[5], val[2], der[2];
     pair(b_ql(k), v);
-    gauss_value_slope_mirror(v, gp, val, der, val_m, der_m);
-    const R ov = partner(val_m), od = partner(der_m);  // the other state at this lane's point
-    ql[k] = R(double(second ? ov : val) + rl[k]);
-    tl2[k] = (second ? od : der) * st2;
-    qr[k] = R(double(second ? val : ov) + rl[k]);
-    tr2[k] = (second ? der : od) * st2;
+    gauss_value_slope2(v, val, der);  // the lane's quantity at -s and +s
+    swap_rows16(val[0], val[1]);       // Q^l and Q^r at the lane's point
+    swap_rows16(der[0], der[1]);
+    ql[k] = R(double(val[0]) + rl[k]);
+    qr[k] = R(double(val[1]) + rl[k]);
+    tl2[k] = der[0] * st2;
+    tr2[k] = der[1] * st2;
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
@@ -503,11 +583,11 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       pair(b_dln(k), pa[k]);
-      R val, val_m;
-      gauss_value_mirror(pa[k], gp, val, val_m);
-      const R o = partner(val_m);
-      dq[0][k] = (second ? o : val) * sn;
-      dq[1][k] = (second ? val : o) * st1;
+      R val[2];
+      gauss_value2(pa[k], val);     // the lane's quantity at -s and +s
+      swap_rows16(val[0], val[1]);  // normal and t1 slope at the lane's point
+      dq[0][k] = val[0] * sn;
+      dq[1][k] = val[1] * st1;
       dq[2][k] = tl2[k];
     }
     flux_side<R, true>(ql, dq, g, acc);
@@ -520,11 +600,11 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       pair(b_drn(k), pa[k]);
-      R val, val_m;
-      gauss_value_mirror(pa[k], gp, val, val_m);
-      const R o = partner(val_m);
-      dq[0][k] = (second ? o : val) * sn;
-      dq[1][k] = (second ? val : o) * st1;
+      R val[2];
+      gauss_value2(pa[k], val);     // the lane's quantity at -s and +s
+      swap_rows16(val[0], val[1]);  // normal and t1 slope at the lane's point
+      dq[0][k] = val[0] * sn;
+      dq[1][k] = val[1] * st1;
       dq[2][k] = tr2[k];
     }
     flux_side<R, false>(qr, dq, g, acc);
@@ -552,36 +632,7 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
     flux_finish(dq0n, g, acc, Fn, Fd);
   }
 
-  // ---- 2x2 Gauss sum across the four lanes of the face -------------------
-  double sn5[5], sd5[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    sn5[k] = double(Fn[k]);
-    sd5[k] = double(Fd[k]);
-    sn5[k] += __shfl_xor(sn5[k], 16);
-    sd5[k] += __shfl_xor(sd5[k], 16);
-    sn5[k] += __shfl_xor(sn5[k], 32);
-    sd5[k] += __shfl_xor(sd5[k], 32);
-  }
-  if (!valid || gpi != 0) return;  // this lane only
-  const double qarea = 0.25 * gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
-  double loc[10];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    loc[k] = qarea * sn5[k];
-    loc[5 + k] = qarea * sd5[k];
-  }
-  const int fpitch = face_pitch(fe[0]);
-  const size_t NF = (size_t)fpitch * fe[1] * fe[2];
-  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fpitch + f[0];
-  // rotate momentum back to the global frame
-  const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
-  HGKS_GLOBAL double* Fg = gmem(F);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    Fg[gcomp[k] * NF + fi] = loc[k];
-    Fg[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
-  }
+  gauss_sum_store<DIR>(P, F, f, valid, gpi, Fn, Fd);
 }
 
 template <int DIR, class R, int TX>
@@ -684,16 +735,15 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     }
   };
   // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
-  // lane ^ 16) share every t2 stencil.  Each reconstructs one of two
-  // quantities at both points (its own and the mirrored one) and swaps the
-  // mirrored result with its partner.  The g2 = 0 lane takes quantity qi0
-  // (Q^l, the normal slopes), the g2 = 1 lane the next one (Q^r, the t1
-  // slopes).
+  // lane ^ 16, an even row and the odd row above it) share every t2
+  // stencil.  Each reconstructs one of two quantities at both points and the
+  // pair exchanges the other point's values (swap_rows16).  The g2 = 0 lane
+  // takes quantity qi0 (Q^l, the normal slopes), the g2 = 1 lane the next
+  // one (Q^r, the t1 slopes).
   auto stencil_pair = [&](int qi0, R v[5]) {
 #pragma unroll
     for (int j = 0; j < 5; ++j) v[j] = *reinterpret_cast<const HGKS_GLOBAL R*>(row_base(qi0, j) + off[j]);
   };
-  auto partner = [](R x) -> R { return R(__shfl_xor(x, 16)); };
 
   // Each phase loads its own raw t2 stencils; the kernels run at least two
   // waves per SIMD (launch bounds), so the other wave covers their latency.
@@ -703,14 +753,15 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   R ql[5], qr[5], tl2[5], tr2[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    R v[5], val, der, val_m, der_m;
+    R v[5], val[2], der[2];
     stencil_pair(b_ql(k), v);
-    gauss_value_slope_mirror(v, gp, val, der, val_m, der_m);
-    const R ov = partner(val_m), od = partner(der_m);  // the other state at this lane's point
-    ql[k] = R(double(second ? ov : val) + rl[k]);
-    tl2[k] = (second ? od : der) * st2;
-    qr[k] = R(double(second ? val : ov) + rl[k]);
-    tr2[k] = (second ? der : od) * st2;
+    gauss_value_slope2(v, val, der);  // the lane's quantity at -s and +s
+    swap_rows16(val[0], val[1]);       // Q^l and Q^r at the lane's point
+    swap_rows16(der[0], der[1]);
+    ql[k] = R(double(val[0]) + rl[k]);
+    qr[k] = R(double(val[1]) + rl[k]);
+    tl2[k] = der[0] * st2;
+    tr2[k] = der[1] * st2;
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
@@ -739,11 +790,11 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       stencil_pair(b_dln(k), pa[k]);
-      R val, val_m;
-      gauss_value_mirror(pa[k], gp, val, val_m);
-      const R o = partner(val_m);
-      dq[0][k] = (second ? o : val) * sn;
-      dq[1][k] = (second ? val : o) * st1;
+      R val[2];
+      gauss_value2(pa[k], val);     // the lane's quantity at -s and +s
+      swap_rows16(val[0], val[1]);  // normal and t1 slope at the lane's point
+      dq[0][k] = val[0] * sn;
+      dq[1][k] = val[1] * st1;
       dq[2][k] = tl2[k];
     }
     flux_side<R, true>(ql, dq, g, acc);
@@ -755,11 +806,11 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       stencil_pair(b_drn(k), pa[k]);
-      R val, val_m;
-      gauss_value_mirror(pa[k], gp, val, val_m);
-      const R o = partner(val_m);
-      dq[0][k] = (second ? o : val) * sn;
-      dq[1][k] = (second ? val : o) * st1;
+      R val[2];
+      gauss_value2(pa[k], val);     // the lane's quantity at -s and +s
+      swap_rows16(val[0], val[1]);  // normal and t1 slope at the lane's point
+      dq[0][k] = val[0] * sn;
+      dq[1][k] = val[1] * st1;
       dq[2][k] = tr2[k];
     }
     flux_side<R, false>(qr, dq, g, acc);
@@ -786,36 +837,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     flux_finish(dq0n, g, acc, Fn, Fd);
   }
 
-  // ---- 2x2 Gauss sum across the four lanes of the face -------------------
-  double sn5[5], sd5[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    sn5[k] = double(Fn[k]);
-    sd5[k] = double(Fd[k]);
-    sn5[k] += __shfl_xor(sn5[k], 16);
-    sd5[k] += __shfl_xor(sd5[k], 16);
-    sn5[k] += __shfl_xor(sn5[k], 32);
-    sd5[k] += __shfl_xor(sd5[k], 32);
-  }
-  if (!valid || gpi != 0) return;  // this lane only
-  const double qarea = 0.25 * gmem(P.hcell[D1])[f[D1]] * gmem(P.hcell[D2])[f[D2]];
-  double loc[10];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    loc[k] = qarea * sn5[k];
-    loc[5 + k] = qarea * sd5[k];
-  }
-  const int fpitch = face_pitch(fe[0]);
-  const size_t NF = (size_t)fpitch * fe[1] * fe[2];
-  const size_t fi = ((size_t)f[2] * fe[1] + f[1]) * fpitch + f[0];
-  // rotate momentum back to the global frame
-  const int gcomp[5] = {0, 1 + DIR, 1 + D1, 1 + D2, 4};
-  HGKS_GLOBAL double* Fg = gmem(F);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    Fg[gcomp[k] * NF + fi] = loc[k];
-    Fg[(5 + gcomp[k]) * NF + fi] = loc[5 + k];
-  }
+  gauss_sum_store<DIR>(P, F, f, valid, gpi, Fn, Fd);
 }
 
 // ---- FP64 flux tiles with the t2 stencil rows shared in LDS (x and z faces) --

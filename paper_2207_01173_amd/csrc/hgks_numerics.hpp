@@ -42,46 +42,48 @@ template <> __device__ __forceinline__ float wz_rcp<float>(float x) { return __b
 // The three quadratic candidates through averages (v0,v1,v2), (v1,v2,v3),
 // (v2,v3,v4), written about the centre cell (x in [-1/2, 1/2]) as
 // p_k(x) = v2 - c_k/24 + b_k x + c_k x^2 / 2: c_k is the candidate's second
-// difference, b_k its slope at the centre.  The Jiang-Shu smoothness
-// indicators are then beta_k = 13/12 c_k^2 + b_k^2.
-template <class R> struct Candidates { R c[3], b[3], beta[3]; };
+// difference, b_k its slope at the centre, both formed from the first
+// differences d_j = v_{j+1} - v_j (c_0 = d_1 - d_0, c_1 = d_2 - d_1,
+// c_2 = d_3 - d_2, b_0 = d_1 + c_0/2, b_1 = (d_1 + d_2)/2, b_2 = d_2 - c_2/2).
+// be_k is the Jiang-Shu smoothness indicator 13/12 c_k^2 + b_k^2 with the
+// WENO-Z epsilon already added.
+template <class R> struct Candidates { R c[3], b[3], be[3]; };
 
 template <class R>
 __device__ __forceinline__ Candidates<R> candidates(const R v[5]) {
   Candidates<R> k;
-  k.c[0] = v[0] - R(2) * v[1] + v[2];
-  k.b[0] = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
-  k.c[1] = v[1] - R(2) * v[2] + v[3];
-  k.b[1] = R(0.5) * (v[3] - v[1]);
-  k.c[2] = v[2] - R(2) * v[3] + v[4];
-  k.b[2] = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
-  const R c13 = R(13.0 / 12.0);
+  const R d0 = v[1] - v[0], d1 = v[2] - v[1], d2 = v[3] - v[2], d3 = v[4] - v[3];
+  k.c[0] = d1 - d0;
+  k.c[1] = d2 - d1;
+  k.c[2] = d3 - d2;
+  k.b[0] = d1 + R(0.5) * k.c[0];
+  k.b[1] = R(0.5) * (d1 + d2);
+  k.b[2] = d2 - R(0.5) * k.c[2];
+  const R c13 = R(13.0 / 12.0), eps = WenoEps<R>::v;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) k.beta[i] = c13 * k.c[i] * k.c[i] + k.b[i] * k.b[i];
+  for (int i = 0; i < 3; ++i) k.be[i] = (c13 * k.c[i]) * k.c[i] + (k.b[i] * k.b[i] + eps);
   return k;
 }
 
 // Nonlinear weights alpha_k = d_k (1 + tau5 / b_k), b_k = beta_k + eps,
-// normalised.  wz_factors gives e_k with alpha_k proportional to d_k e_k; they
-// depend on the stencil only, so every set of linear weights (both Gauss
-// points, value and slope weights) shares them.  Multiplying every alpha by
-// b0 b1 b2 leaves the normalised weights unchanged and needs a single
-// reciprocal per set (FP64: the products stay far from underflow for b >=
-// eps).  The FP32 path keeps one reciprocal per b_k, whose products could
-// underflow.
+// tau5 = |beta_0 - beta_2|, normalised.  wz_factors gives e_k with alpha_k
+// proportional to d_k e_k; they depend on the stencil only, so every set of
+// linear weights (both Gauss points, value and slope weights) shares them.
+// Multiplying every alpha by b0 b1 b2 leaves the normalised weights unchanged
+// and needs a single reciprocal per set (FP64: the products stay far from
+// underflow for b >= eps).  The FP32 path keeps one reciprocal per b_k,
+// whose products could underflow.
 template <class R>
-__device__ __forceinline__ void wz_factors(const R beta[3], R e[3]) {
-  const R eps = WenoEps<R>::v;
-  const R t5 = fabs(beta[0] - beta[2]);
-  const R b0 = beta[0] + eps, b1 = beta[1] + eps, b2 = beta[2] + eps;
+__device__ __forceinline__ void wz_factors(const R be[3], R e[3]) {
+  const R t5 = fabs(be[0] - be[2]);
   if (sizeof(R) == 8) {
-    e[0] = (b0 + t5) * (b1 * b2);
-    e[1] = (b1 + t5) * (b0 * b2);
-    e[2] = (b2 + t5) * (b0 * b1);
+    e[0] = (be[0] + t5) * (be[1] * be[2]);
+    e[1] = (be[1] + t5) * (be[0] * be[2]);
+    e[2] = (be[2] + t5) * (be[0] * be[1]);
   } else {
-    e[0] = R(1) + t5 * pos_rcp(b0);
-    e[1] = R(1) + t5 * pos_rcp(b1);
-    e[2] = R(1) + t5 * pos_rcp(b2);
+    e[0] = R(1) + t5 * pos_rcp(be[0]);
+    e[1] = R(1) + t5 * pos_rcp(be[1]);
+    e[2] = R(1) + t5 * pos_rcp(be[2]);
   }
 }
 
@@ -114,55 +116,60 @@ struct GaussConst {
 // Position and linear weights of one Gauss point, chosen per lane at run time
 // (g = 0: s = -sqrt3/6, g = 1: s = +sqrt3/6; the weights mirror with s).
 template <class R> struct GaussPoint {
-  R s, dv0, dv1, dv2, dd0, dd1, dd2;
+  R s, dv0, dv1, dv2;
   __device__ __forceinline__ explicit GaussPoint(int g) {
     const bool p = g != 0;
     s = p ? R(GaussConst::s) : R(-GaussConst::s);
     dv0 = p ? R(GaussConst::dv0) : R(GaussConst::dv2);
     dv1 = R(GaussConst::dv1);
     dv2 = p ? R(GaussConst::dv2) : R(GaussConst::dv0);
-    dd0 = p ? R(GaussConst::dd0) : R(GaussConst::dd2);
-    dd1 = R(GaussConst::dd1);
-    dd2 = p ? R(GaussConst::dd2) : R(GaussConst::dd0);
   }
 };
 
-// At a Gauss point (s^2 = 1/12) the candidate value is v2 + b_k s and its
-// slope b_k + c_k s.
-
 // Both Gauss points of one stencil (index 0: s = -sqrt3/6, 1: s = +sqrt3/6)
-// from one set of candidates and WENO-Z factors: at each point the value
-// v2 + s sum w_k b_k with the value weights of that point, and the slope
-// sum w_k (b_k + c_k s) with its slope weights.
+// from one set of candidates and WENO-Z factors.  At +s the value is
+// v2 + s sum w_k b_k with the value weights (dv0, dv1, dv2) and the slope
+// sum w_k (b_k + s c_k) with the slope weights (dd0, dd1, dd2); at -s the
+// weights are reversed and s changes sign.  With y_k = e_k b_k and
+// z_k = e_k c_k every such sum is (sum_k d_k y_k [+- s sum_k d_k z_k]) /
+// sum_k d_k e_k, the factors s d_k being constants.
 template <class R>
 __device__ __forceinline__ void gauss_value2(const R v[5], R val[2]) {
+  using G = GaussConst;
   const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  const R s = R(GaussConst::s);
-  const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
-  R inv = wz_alpha(e, d2, d1, d0, a);
-  val[0] = v[2] - s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, d0, d1, d2, a);
-  val[1] = v[2] + s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
+  R e[3];
+  wz_factors(k.be, e);
+  const R y0 = e[0] * k.b[0], y1 = e[1] * k.b[1], y2 = e[2] * k.b[2];
+  const R nm = R(G::s * G::dv2) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv0) * y2;
+  const R dm = R(G::dv2) * e[0] + R(G::dv1) * e[1] + R(G::dv0) * e[2];
+  const R np = R(G::s * G::dv0) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv2) * y2;
+  const R dp = R(G::dv0) * e[0] + R(G::dv1) * e[1] + R(G::dv2) * e[2];
+  val[0] = v[2] - nm * wz_rcp(dm);
+  val[1] = v[2] + np * wz_rcp(dp);
 }
 
 template <class R>
 __device__ __forceinline__ void gauss_value_slope2(const R v[5], R val[2], R der[2]) {
+  using G = GaussConst;
   const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  const R s = R(GaussConst::s);
-  const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
-  const R g0 = R(GaussConst::dd0), g1 = R(GaussConst::dd1), g2 = R(GaussConst::dd2);
-  R inv = wz_alpha(e, d2, d1, d0, a);
-  val[0] = v[2] - s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, g2, g1, g0, a);
-  der[0] = inv * wz_dot(a, k.b[0] - k.c[0] * s, k.b[1] - k.c[1] * s, k.b[2] - k.c[2] * s);
-  inv = wz_alpha(e, d0, d1, d2, a);
-  val[1] = v[2] + s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, g0, g1, g2, a);
-  der[1] = inv * wz_dot(a, k.b[0] + k.c[0] * s, k.b[1] + k.c[1] * s, k.b[2] + k.c[2] * s);
+  R e[3];
+  wz_factors(k.be, e);
+  const R y0 = e[0] * k.b[0], y1 = e[1] * k.b[1], y2 = e[2] * k.b[2];
+  const R z0 = e[0] * k.c[0], z1 = e[1] * k.c[1], z2 = e[2] * k.c[2];
+  const R nm = R(G::s * G::dv2) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv0) * y2;
+  const R dm = R(G::dv2) * e[0] + R(G::dv1) * e[1] + R(G::dv0) * e[2];
+  const R np = R(G::s * G::dv0) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv2) * y2;
+  const R dp = R(G::dv0) * e[0] + R(G::dv1) * e[1] + R(G::dv2) * e[2];
+  val[0] = v[2] - nm * wz_rcp(dm);
+  val[1] = v[2] + np * wz_rcp(dp);
+  const R sm = R(G::dd2) * y0 + R(G::dd1) * y1 + R(G::dd0) * y2 + R(-G::s * G::dd2) * z0 +
+               R(-G::s * G::dd1) * z1 + R(-G::s * G::dd0) * z2;
+  const R em = R(G::dd2) * e[0] + R(G::dd1) * e[1] + R(G::dd0) * e[2];
+  const R sp = R(G::dd0) * y0 + R(G::dd1) * y1 + R(G::dd2) * y2 + R(G::s * G::dd0) * z0 +
+               R(G::s * G::dd1) * z1 + R(G::s * G::dd2) * z2;
+  const R ep = R(G::dd0) * e[0] + R(G::dd1) * e[1] + R(G::dd2) * e[2];
+  der[0] = sm * wz_rcp(em);
+  der[1] = sp * wz_rcp(ep);
 }
 
 template <class R>
@@ -174,36 +181,6 @@ __device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
   const R d0 = R(GaussConst::dv0), d1 = R(GaussConst::dv1), d2 = R(GaussConst::dv2);
   val[0] = v[2] - s * (d2 * b0 + d1 * b1 + d0 * b2);
   val[1] = v[2] + s * (d0 * b0 + d1 * b1 + d2 * b2);
-}
-
-// WENO-Z at a lane's Gauss point (gp) and at the mirrored point -s (whose
-// linear weights are gp's reversed), from one set of candidates and factors;
-// at each point the same value and slope as gauss_value_slope2.
-template <class R>
-__device__ __forceinline__ void gauss_value_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& val_m) {
-  const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
-  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, gp.dv2, gp.dv1, gp.dv0, a);
-  val_m = v[2] - gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-}
-
-template <class R>
-__device__ __forceinline__ void gauss_value_slope_mirror(const R v[5], const GaussPoint<R>& gp, R& val, R& der,
-                                                         R& val_m, R& der_m) {
-  const Candidates<R> k = candidates(v);
-  R e[3], a[3];
-  wz_factors(k.beta, e);
-  R inv = wz_alpha(e, gp.dv0, gp.dv1, gp.dv2, a);
-  val = v[2] + gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, gp.dd0, gp.dd1, gp.dd2, a);
-  der = inv * wz_dot(a, k.b[0] + k.c[0] * gp.s, k.b[1] + k.c[1] * gp.s, k.b[2] + k.c[2] * gp.s);
-  inv = wz_alpha(e, gp.dv2, gp.dv1, gp.dv0, a);
-  val_m = v[2] - gp.s * inv * wz_dot(a, k.b[0], k.b[1], k.b[2]);
-  inv = wz_alpha(e, gp.dd2, gp.dd1, gp.dd0, a);
-  der_m = inv * wz_dot(a, k.b[0] - k.c[0] * gp.s, k.b[1] - k.c[1] * gp.s, k.b[2] - k.c[2] * gp.s);
 }
 
 // Linear (fifth-order) value at a Gauss point: the quartic through the averages.
@@ -221,7 +198,7 @@ template <class R>
 __device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
   const Candidates<R> k = candidates(v);
   R e[3], a[3];
-  wz_factors(k.beta, e);
+  wz_factors(k.be, e);
   const R inv = wz_alpha(e, R(0.1), R(0.6), R(0.3), a);
   const R twelfth = R(1.0 / 12.0);
   val = v[2] + inv * wz_dot(a, R(0.5) * k.b[0] + twelfth * k.c[0], R(0.5) * k.b[1] + twelfth * k.c[1],
