@@ -48,6 +48,7 @@ struct Params {
   int flags;  // hgks_config.flags
   double gamma, gm1, K, mu_ref, T_ref, mu_exp, pr_fix, T_wall;
   double iK3, iT_ref;  // 1/(K + 3); 1/T_ref (0 without a power law)
+  double imu_ref;      // 1/mu_ref (0 for an inviscid gas)
   double force[3];
   const double* hcell[3];  // cell widths
   const double* dface[3];  // d(index)/dx at faces 0..n
@@ -527,6 +528,7 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
   g.iK3 = R(P.iK3);
   g.mu_ref = R(P.mu_ref);
   g.iT_ref = R(P.iT_ref);
+  g.imu_ref = R(P.imu_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
   // Gauss-point pairs: the lanes g2 = 0 and g2 = 1 of a Gauss line (lane and
@@ -720,6 +722,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   g.iK3 = R(P.iK3);
   g.mu_ref = R(P.mu_ref);
   g.iT_ref = R(P.iT_ref);
+  g.imu_ref = R(P.imu_ref);
   g.mu_exp = R(P.mu_exp);
   g.pr_fix = R(P.pr_fix);
   // Wave-uniform base of quantity qi and stencil row j.
@@ -1565,6 +1568,7 @@ Params make_params(const hgks_config& c) {
   P.T_wall = c.T_wall;
   P.iK3 = 1.0 / (P.K + 3.0);
   P.iT_ref = c.T_ref > 0.0 ? 1.0 / c.T_ref : 0.0;
+  P.imu_ref = c.mu_ref > 0.0 ? 1.0 / c.mu_ref : 0.0;
   return P;
 }
 

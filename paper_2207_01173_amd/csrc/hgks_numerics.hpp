@@ -39,15 +39,33 @@ template <> __device__ __forceinline__ double wz_rcp<double>(double x) {
 }
 template <> __device__ __forceinline__ float wz_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reciprocals of the two weight sums of a Gauss-point pair.  FP64: both from
+// one reciprocal of their product (the hardware reciprocal issues at a
+// quarter of the FMA rate; the sums lie between about 1e-60 and the sixth
+// power of the data's squared variation, so the product stays in range);
+// FP32, whose sums can reach 1e20, one each.
+template <class R> __device__ __forceinline__ void wz_rcp2(R x, R y, R& ix, R& iy);
+template <> __device__ __forceinline__ void wz_rcp2<double>(double x, double y, double& ix, double& iy) {
+  const double r = wz_rcp(x * y);
+  ix = y * r;
+  iy = x * r;
+}
+template <> __device__ __forceinline__ void wz_rcp2<float>(float x, float y, float& ix, float& iy) {
+  ix = wz_rcp(x);
+  iy = wz_rcp(y);
+}
+
 // The three quadratic candidates through averages (v0,v1,v2), (v1,v2,v3),
 // (v2,v3,v4), written about the centre cell (x in [-1/2, 1/2]) as
 // p_k(x) = v2 - c_k/24 + b_k x + c_k x^2 / 2: c_k is the candidate's second
 // difference, b_k its slope at the centre, both formed from the first
-// differences d_j = v_{j+1} - v_j (c_0 = d_1 - d_0, c_1 = d_2 - d_1,
-// c_2 = d_3 - d_2, b_0 = d_1 + c_0/2, b_1 = (d_1 + d_2)/2, b_2 = d_2 - c_2/2).
-// be_k is the Jiang-Shu smoothness indicator 13/12 c_k^2 + b_k^2 with the
-// WENO-Z epsilon already added.
-template <class R> struct Candidates { R c[3], b[3], be[3]; };
+// differences d_j = v_{j+1} - v_j: c_0 = d_1 - d_0, c_1 = d_2 - d_1,
+// c_2 = d_3 - d_2, and tb_k = 2 b_k: tb_0 = 2 d_1 + c_0, tb_1 = d_1 + d_2,
+// tb_2 = 2 d_2 - c_2.  be_k = 13/3 c_k^2 + tb_k^2 + 4 eps is four times the
+// Jiang-Shu smoothness indicator 13/12 c_k^2 + b_k^2 plus the WENO-Z
+// epsilon: the normalised weights do not change when every indicator and
+// tau5 are scaled alike.
+template <class R> struct Candidates { R c[3], tb[3], be[3]; };
 
 template <class R>
 __device__ __forceinline__ Candidates<R> candidates(const R v[5]) {
@@ -56,17 +74,18 @@ __device__ __forceinline__ Candidates<R> candidates(const R v[5]) {
   k.c[0] = d1 - d0;
   k.c[1] = d2 - d1;
   k.c[2] = d3 - d2;
-  k.b[0] = d1 + R(0.5) * k.c[0];
-  k.b[1] = R(0.5) * (d1 + d2);
-  k.b[2] = d2 - R(0.5) * k.c[2];
-  const R c13 = R(13.0 / 12.0), eps = WenoEps<R>::v;
+  k.tb[0] = R(2) * d1 + k.c[0];
+  k.tb[1] = d1 + d2;
+  k.tb[2] = R(2) * d2 - k.c[2];
+  const R c13 = R(13.0 / 3.0), eps4 = R(4) * WenoEps<R>::v;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) k.be[i] = (c13 * k.c[i]) * k.c[i] + (k.b[i] * k.b[i] + eps);
+  for (int i = 0; i < 3; ++i) k.be[i] = (c13 * k.c[i]) * k.c[i] + (k.tb[i] * k.tb[i] + eps4);
   return k;
 }
 
 // Nonlinear weights alpha_k = d_k (1 + tau5 / b_k), b_k = beta_k + eps,
-// tau5 = |beta_0 - beta_2|, normalised.  wz_factors gives e_k with alpha_k
+// tau5 = |beta_0 - beta_2|, normalised (from be_k = 4 b_k and 4 tau5, the
+// same weights).  wz_factors gives e_k with alpha_k
 // proportional to d_k e_k; they depend on the stencil only, so every set of
 // linear weights (both Gauss points, value and slope weights) shares them.
 // Multiplying every alpha by b0 b1 b2 leaves the normalised weights unchanged
@@ -77,9 +96,12 @@ template <class R>
 __device__ __forceinline__ void wz_factors(const R be[3], R e[3]) {
   const R t5 = fabs(be[0] - be[2]);
   if (sizeof(R) == 8) {
-    e[0] = (be[0] + t5) * (be[1] * be[2]);
-    e[1] = (be[1] + t5) * (be[0] * be[2]);
-    e[2] = (be[2] + t5) * (be[0] * be[1]);
+    // e_k = (b_k + tau5) prod_{j != k} b_j = P + tau5 prod_{j != k} b_j
+    const R q12 = be[1] * be[2], q02 = be[0] * be[2], q01 = be[0] * be[1];
+    const R P = be[0] * q12;
+    e[0] = P + t5 * q12;
+    e[1] = P + t5 * q02;
+    e[2] = P + t5 * q01;
   } else {
     e[0] = R(1) + t5 * pos_rcp(be[0]);
     e[1] = R(1) + t5 * pos_rcp(be[1]);
@@ -130,22 +152,25 @@ template <class R> struct GaussPoint {
 // from one set of candidates and WENO-Z factors.  At +s the value is
 // v2 + s sum w_k b_k with the value weights (dv0, dv1, dv2) and the slope
 // sum w_k (b_k + s c_k) with the slope weights (dd0, dd1, dd2); at -s the
-// weights are reversed and s changes sign.  With y_k = e_k b_k and
-// z_k = e_k c_k every such sum is (sum_k d_k y_k [+- s sum_k d_k z_k]) /
-// sum_k d_k e_k, the factors s d_k being constants.
+// weights are reversed and s changes sign.  With y_k = e_k tb_k = 2 e_k b_k
+// and z_k = e_k c_k every such sum is
+// (sum_k (d_k/2) y_k [+- s sum_k d_k z_k]) / sum_k d_k e_k, the factors
+// being constants.
 template <class R>
 __device__ __forceinline__ void gauss_value2(const R v[5], R val[2]) {
   using G = GaussConst;
   const Candidates<R> k = candidates(v);
   R e[3];
   wz_factors(k.be, e);
-  const R y0 = e[0] * k.b[0], y1 = e[1] * k.b[1], y2 = e[2] * k.b[2];
-  const R nm = R(G::s * G::dv2) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv0) * y2;
+  const R y0 = e[0] * k.tb[0], y1 = e[1] * k.tb[1], y2 = e[2] * k.tb[2];
+  const R nm = R(0.5 * G::s * G::dv2) * y0 + R(0.5 * G::s * G::dv1) * y1 + R(0.5 * G::s * G::dv0) * y2;
   const R dm = R(G::dv2) * e[0] + R(G::dv1) * e[1] + R(G::dv0) * e[2];
-  const R np = R(G::s * G::dv0) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv2) * y2;
+  const R np = R(0.5 * G::s * G::dv0) * y0 + R(0.5 * G::s * G::dv1) * y1 + R(0.5 * G::s * G::dv2) * y2;
   const R dp = R(G::dv0) * e[0] + R(G::dv1) * e[1] + R(G::dv2) * e[2];
-  val[0] = v[2] - nm * wz_rcp(dm);
-  val[1] = v[2] + np * wz_rcp(dp);
+  R im, ip;
+  wz_rcp2(dm, dp, im, ip);
+  val[0] = v[2] - nm * im;
+  val[1] = v[2] + np * ip;
 }
 
 template <class R>
@@ -154,22 +179,25 @@ __device__ __forceinline__ void gauss_value_slope2(const R v[5], R val[2], R der
   const Candidates<R> k = candidates(v);
   R e[3];
   wz_factors(k.be, e);
-  const R y0 = e[0] * k.b[0], y1 = e[1] * k.b[1], y2 = e[2] * k.b[2];
+  const R y0 = e[0] * k.tb[0], y1 = e[1] * k.tb[1], y2 = e[2] * k.tb[2];
   const R z0 = e[0] * k.c[0], z1 = e[1] * k.c[1], z2 = e[2] * k.c[2];
-  const R nm = R(G::s * G::dv2) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv0) * y2;
+  const R nm = R(0.5 * G::s * G::dv2) * y0 + R(0.5 * G::s * G::dv1) * y1 + R(0.5 * G::s * G::dv0) * y2;
   const R dm = R(G::dv2) * e[0] + R(G::dv1) * e[1] + R(G::dv0) * e[2];
-  const R np = R(G::s * G::dv0) * y0 + R(G::s * G::dv1) * y1 + R(G::s * G::dv2) * y2;
+  const R np = R(0.5 * G::s * G::dv0) * y0 + R(0.5 * G::s * G::dv1) * y1 + R(0.5 * G::s * G::dv2) * y2;
   const R dp = R(G::dv0) * e[0] + R(G::dv1) * e[1] + R(G::dv2) * e[2];
-  val[0] = v[2] - nm * wz_rcp(dm);
-  val[1] = v[2] + np * wz_rcp(dp);
-  const R sm = R(G::dd2) * y0 + R(G::dd1) * y1 + R(G::dd0) * y2 + R(-G::s * G::dd2) * z0 +
+  R im, ip;
+  wz_rcp2(dm, dp, im, ip);
+  val[0] = v[2] - nm * im;
+  val[1] = v[2] + np * ip;
+  const R sm = R(0.5 * G::dd2) * y0 + R(0.5 * G::dd1) * y1 + R(0.5 * G::dd0) * y2 + R(-G::s * G::dd2) * z0 +
                R(-G::s * G::dd1) * z1 + R(-G::s * G::dd0) * z2;
   const R em = R(G::dd2) * e[0] + R(G::dd1) * e[1] + R(G::dd0) * e[2];
-  const R sp = R(G::dd0) * y0 + R(G::dd1) * y1 + R(G::dd2) * y2 + R(G::s * G::dd0) * z0 +
+  const R sp = R(0.5 * G::dd0) * y0 + R(0.5 * G::dd1) * y1 + R(0.5 * G::dd2) * y2 + R(G::s * G::dd0) * z0 +
                R(G::s * G::dd1) * z1 + R(G::s * G::dd2) * z2;
   const R ep = R(G::dd0) * e[0] + R(G::dd1) * e[1] + R(G::dd2) * e[2];
-  der[0] = sm * wz_rcp(em);
-  der[1] = sp * wz_rcp(ep);
+  wz_rcp2(em, ep, im, ip);
+  der[0] = sm * im;
+  der[1] = sp * ip;
 }
 
 template <class R>
@@ -193,7 +221,8 @@ __device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp)
 }
 
 // Value and slope at the right face (s = 1/2) of the centre cell: candidate
-// value v2 + b_k/2 + c_k/12, slope b_k + c_k/2.
+// value v2 + b_k/2 + c_k/12 = v2 + tb_k/4 + c_k/12, slope b_k + c_k/2 =
+// (tb_k + c_k)/2.
 template <class R>
 __device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
   const Candidates<R> k = candidates(v);
@@ -201,9 +230,9 @@ __device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
   wz_factors(k.be, e);
   const R inv = wz_alpha(e, R(0.1), R(0.6), R(0.3), a);
   const R twelfth = R(1.0 / 12.0);
-  val = v[2] + inv * wz_dot(a, R(0.5) * k.b[0] + twelfth * k.c[0], R(0.5) * k.b[1] + twelfth * k.c[1],
-                            R(0.5) * k.b[2] + twelfth * k.c[2]);
-  der = inv * wz_dot(a, k.b[0] + R(0.5) * k.c[0], k.b[1] + R(0.5) * k.c[1], k.b[2] + R(0.5) * k.c[2]);
+  val = v[2] + inv * wz_dot(a, R(0.25) * k.tb[0] + twelfth * k.c[0], R(0.25) * k.tb[1] + twelfth * k.c[1],
+                            R(0.25) * k.tb[2] + twelfth * k.c[2]);
+  der = (R(0.5) * inv) * wz_dot(a, k.tb[0] + k.c[0], k.tb[1] + k.c[1], k.tb[2] + k.c[2]);
 }
 
 // Normal sweep at face i+1/2 from c[0..5] = Q_{i-2..i+3}: left/right values and
@@ -249,12 +278,90 @@ __device__ __forceinline__ void chain(R mean, R ihl, R m0, R m1, R o[N]) {
   for (int n = 0; n + 2 < N; ++n) o[n + 2] = mean * o[n + 1] + R(n + 1) * ihl * o[n];
 }
 
-// Zeroth and first half-space u-moments, u > 0 (SIDE = +1) or u < 0 (SIDE = -1).
+// sqrt(x) and 1/sqrt(x) of a positive, normal number.  FP64: the hardware
+// reciprocal-square-root estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2 (the estimate's relative error squares at each
+// step, leaving a few ulp), sqrt(x) = x y.  FP32: sqrt and its hardware
+// reciprocal.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& sq, double& rs) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  rs = y;
+  sq = x * y;
+}
+__device__ __forceinline__ void sqrt_rsqrt(float x, float& sq, float& rs) {
+  sq = sqrtf(x);
+  rs = __builtin_amdgcn_rcpf(sq);
+}
+
+// n! as a compile-time constant.
+template <int N> struct Factorial { static constexpr double value = N * Factorial<N - 1>::value; };
+template <> struct Factorial<0> { static constexpr double value = 1.0; };
+
+// Taylor coefficients in t = x^2: e^{-t} = sum_n (-t)^n / n!, and
+// erf(x) / x = 2/sqrt(pi) sum_n (-t)^n / (n! (2n + 1)).
+struct ExpNegSeries {
+  template <int n> static constexpr double coef() { return ((n & 1) ? -1.0 : 1.0) / Factorial<n>::value; }
+};
+struct ErfSeries {
+  template <int n> static constexpr double coef() {
+    return 1.1283791670955125739 * ((n & 1) ? -1.0 : 1.0) / (Factorial<n>::value * (2 * n + 1));
+  }
+};
+// A compile-time constant held in scalar registers for the one FMA that
+// reads it.  As an FMA's addend the compiler would otherwise copy it into
+// vector registers first (two VALU moves per FP64 constant, for the
+// two-operand FMA form); from scalar registers it is an operand of the
+// three-operand form, and the scalar moves issue beside another wave's VALU
+// work.
+template <class R> __device__ __forceinline__ R in_sgpr(R c) {
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
+// sum_{n <= N} S::coef<n>() t^n in Horner form (p enters as the t^N coefficient).
+template <class R, class S, int N>
+__device__ __forceinline__ R horner(R t, R p) {
+  if constexpr (N == 0) {
+    return p;
+  } else {
+    return horner<R, S, N - 1>(t, p * t + in_sgpr(R(S::template coef<N - 1>())));
+  }
+}
+template <class R, class S, int N> __device__ __forceinline__ R series(R t) {
+  return horner<R, S, N>(t, R(S::template coef<N>()));
+}
+// Degrees for |x| <= 1/2 (t <= 1/4): the first omitted term is below 3e-18
+// (FP64) or 4e-10 (FP32) of the sum.
+template <class R> struct HalfSeries;
+template <> struct HalfSeries<double> { static constexpr int kExp = 12, kErf = 11; };
+template <> struct HalfSeries<float> { static constexpr int kExp = 7, kErf = 6; };
+
+// Zeroth and first half-space u-moments, u > 0 (SIDE = +1) or u < 0 (SIDE = -1):
+// with x = sqrt(lambda) U, m0 = erfc(-SIDE x) / 2 and
+// m1 = U m0 + SIDE e^{-x^2} / (2 sqrt(pi lambda)).  For |x| <= 1/2 (the
+// low-Mach states) e^{-x^2} and erf(x) come from their Taylor series, and
+// erfc(-SIDE x) = 1 + SIDE erf(x); elsewhere from the device library.
 template <class R, int SIDE>
 __device__ __forceinline__ void half_moments01(const State<R>& s, R& m0, R& m1) {
-  R sl = sqrt(s.lam);
-  R e = exp(-s.lam * s.U * s.U) * R(0.28209479177387814347) * pos_rcp(sl);  // e^{-l U^2} / (2 sqrt(pi l))
-  m0 = R(0.5) * erfc(-R(SIDE) * sl * s.U);
+  R sl, isl;
+  sqrt_rsqrt(s.lam, sl, isl);
+  const R x = sl * s.U;
+  R ex, ec;
+  if (fabs(x) <= R(0.5)) {
+    const R t = x * x;
+    ex = series<R, ExpNegSeries, HalfSeries<R>::kExp>(t);
+    ec = R(1) + R(SIDE) * (x * series<R, ErfSeries, HalfSeries<R>::kErf>(t));
+  } else {
+    ex = exp(-s.lam * s.U * s.U);
+    ec = erfc(-R(SIDE) * x);
+  }
+  const R e = ex * R(0.28209479177387814347) * isl;  // e^{-l U^2} / (2 sqrt(pi l))
+  m0 = R(0.5) * ec;
   m1 = s.U * m0 + R(SIDE) * e;
 }
 
@@ -304,18 +411,6 @@ __device__ __forceinline__ Quad<R> quad_p(const R a[5], const VW<R>& e) {
   return {a[0] + a[2] * e.v + a[3] * e.w + h * e.r, a[0] * e.v + a[2] * e.vv + a[3] * e.vw + h * e.vr,
           a[0] * e.w + a[2] * e.vw + a[3] * e.ww + h * e.wr, a[0] * e.r + a[2] * e.vr + a[3] * e.wr + h * e.rr};
 }
-template <class R>
-__device__ __forceinline__ Quad<R> quad_vp(const R a[5], const VW<R>& e) {
-  const R h = R(0.5) * a[4];
-  return {a[0] * e.v + a[2] * e.vv + a[3] * e.vw + h * e.vr, a[0] * e.vv + a[2] * e.vvv + a[3] * e.vvw + h * e.vvr,
-          a[0] * e.vw + a[2] * e.vvw + a[3] * e.vww + h * e.vwr, a[0] * e.vr + a[2] * e.vvr + a[3] * e.vwr + h * e.vrr};
-}
-template <class R>
-__device__ __forceinline__ Quad<R> quad_wp(const R a[5], const VW<R>& e) {
-  const R h = R(0.5) * a[4];
-  return {a[0] * e.w + a[2] * e.vw + a[3] * e.ww + h * e.wr, a[0] * e.vw + a[2] * e.vvw + a[3] * e.vww + h * e.vwr,
-          a[0] * e.ww + a[2] * e.vww + a[3] * e.www + h * e.wwr, a[0] * e.wr + a[2] * e.vwr + a[3] * e.wwr + h * e.wrr};
-}
 // Quad of c (1, v, w, r-weighted): c times the unit polynomial.
 template <class R>
 __device__ __forceinline__ Quad<R> quad_c(R c, const VW<R>& e) {
@@ -327,11 +422,6 @@ __device__ __forceinline__ Quad<R> quad_lin(R c0, R c1, R c2, const VW<R>& e) {
   return {c0 + c1 * e.v + c2 * e.w, c0 * e.v + c1 * e.vv + c2 * e.vw, c0 * e.w + c1 * e.vw + c2 * e.ww,
           c0 * e.r + c1 * e.vr + c2 * e.wr};
 }
-template <class R>
-__device__ __forceinline__ Quad<R> qadd(const Quad<R>& a, const Quad<R>& b) {
-  return {a.e0 + b.e0, a.ev + b.ev, a.ew + b.ew, a.er + b.er};
-}
-
 // <u^X G psi> for G = sum_{i < NS} u^i g_i, given the quads of the g_i and a
 // u-moment table Mu (full or half space), psi = (1, u, v, w, (u^2 + r)/2).
 template <class R, int X, int NS>
@@ -352,38 +442,80 @@ __device__ __forceinline__ void assemble(const Quad<R> q[NS], const R Mu[7], R o
   o[4] = R(0.5) * a4;
 }
 
-// u-series of a . psi: (p, a1, h).
-template <class R>
-__device__ __forceinline__ void series_apsi(const R a[5], const VW<R>& e, Quad<R> q[3]) {
-  q[0] = quad_p(a, e);
-  q[1] = quad_c(a[1], e);
-  q[2] = quad_c(R(0.5) * a[4], e);
-}
-
 // u-series of Pi = u (an . psi) + v (at1 . psi) + w (at2 . psi):
 // Pi_0 = v p_t1 + w p_t2, Pi_1 = p_n + at1_1 v + at2_1 w, Pi_2 = an_1 + h_t1 v + h_t2 w, Pi_3 = h_n.
+// Each term's coefficients are gathered per monomial before its moments are
+// taken: Pi_0 = at1_0 v + at2_0 w + at1_2 v^2 + (at1_3 + at2_2) v w + at2_3 w^2
+// + h_t1 v r + h_t2 w r, and Pi_1 is p of (an_0, ., an_2 + at1_1, an_3 + at2_1, an_4).
 template <class R>
 __device__ __forceinline__ void series_pi(const R a[3][5], const VW<R>& e, Quad<R> q[4]) {
-  q[0] = qadd(quad_vp(a[1], e), quad_wp(a[2], e));
-  q[1] = qadd(quad_p(a[0], e), quad_lin(R(0), a[1][1], a[2][1], e));
-  q[2] = quad_lin(a[0][1], R(0.5) * a[1][4], R(0.5) * a[2][4], e);
+  const R h1 = R(0.5) * a[1][4], h2 = R(0.5) * a[2][4];
+  const R cvw = a[1][3] + a[2][2];
+  q[0].e0 = a[1][0] * e.v + a[2][0] * e.w + a[1][2] * e.vv + cvw * e.vw + a[2][3] * e.ww + h1 * e.vr + h2 * e.wr;
+  q[0].ev = a[1][0] * e.vv + a[2][0] * e.vw + a[1][2] * e.vvv + cvw * e.vvw + a[2][3] * e.vww + h1 * e.vvr +
+            h2 * e.vwr;
+  q[0].ew = a[1][0] * e.vw + a[2][0] * e.ww + a[1][2] * e.vvw + cvw * e.vww + a[2][3] * e.www + h1 * e.vwr +
+            h2 * e.wwr;
+  q[0].er = a[1][0] * e.vr + a[2][0] * e.wr + a[1][2] * e.vvr + cvw * e.vwr + a[2][3] * e.wwr + h1 * e.vrr +
+            h2 * e.wrr;
+  const R p1[5] = {a[0][0], R(0), a[0][2] + a[1][1], a[0][3] + a[2][1], a[0][4]};
+  q[1] = quad_p(p1, e);
+  q[2] = quad_lin(a[0][1], h1, h2, e);
   q[3] = quad_c(R(0.5) * a[0][4], e);
 }
 
-// Closed-form solution of <(a . psi) psi> = b for a Maxwellian state.
+// Closed-form solution of <(a . psi) psi> = c b for a Maxwellian state
+// (normalised by density).  The common scale c of the right-hand side (1/rho
+// for slopes of conserved variables, -1 for the time-derivative condition)
+// is folded into the solve's constants: t1 = 2 lambda c and
+// t2 = (2 lambda)^2 c / (K + 3).
+template <class R> struct SlopeSolve { R U, V, W, q2, c, t1, t2; };
+
 template <class R>
-__device__ __forceinline__ void slope_solve(const State<R>& s, R ihl, R K3, R iK3, const R b[5], R a[5]) {
-  R q2 = s.U * s.U + s.V * s.V + s.W * s.W + K3 * ihl;
-  R r2 = b[1] - s.U * b[0];
-  R r3 = b[2] - s.V * b[0];
-  R r4 = b[3] - s.W * b[0];
-  R r5 = R(2) * b[4] - q2 * b[0];
-  R tl = R(2) * s.lam;
-  a[4] = tl * tl * iK3 * (r5 - R(2) * (s.U * r2 + s.V * r3 + s.W * r4));
-  a[3] = tl * r4 - s.W * a[4];
-  a[2] = tl * r3 - s.V * a[4];
-  a[1] = tl * r2 - s.U * a[4];
-  a[0] = b[0] - s.U * a[1] - s.V * a[2] - s.W * a[3] - R(0.5) * a[4] * q2;
+__device__ __forceinline__ SlopeSolve<R> slope_solver(const State<R>& s, R ihl, R K3, R iK3, R c) {
+  SlopeSolve<R> S;
+  S.U = s.U;
+  S.V = s.V;
+  S.W = s.W;
+  S.q2 = s.U * s.U + s.V * s.V + s.W * s.W + K3 * ihl;
+  const R tl = R(2) * s.lam;
+  S.c = c;
+  S.t1 = tl * c;
+  S.t2 = tl * tl * iK3 * c;
+  return S;
+}
+
+template <class R>
+__device__ __forceinline__ void slope_solve(const SlopeSolve<R>& S, const R b[5], R a[5]) {
+  const R r2 = b[1] - S.U * b[0];
+  const R r3 = b[2] - S.V * b[0];
+  const R r4 = b[3] - S.W * b[0];
+  const R r5 = R(2) * b[4] - S.q2 * b[0];
+  a[4] = S.t2 * (r5 - R(2) * (S.U * r2 + S.V * r3 + S.W * r4));
+  a[3] = S.t1 * r4 - S.W * a[4];
+  a[2] = S.t1 * r3 - S.V * a[4];
+  a[1] = S.t1 * r2 - S.U * a[4];
+  a[0] = S.c * b[0] - S.U * a[1] - S.V * a[2] - S.W * a[3] - R(0.5) * a[4] * S.q2;
+}
+
+// <u^X (a . psi) psi> for a u-moment table Mu, in closed form.  With
+// p = a0 + a2 v + a3 w + h r (h = a4/2), (a . psi) = p + a1 u + h u^2; qp
+// holds the (v, w, xi)-moments of p (quad_p) and c = Mu[X+1] a1 + Mu[X+2] h:
+//   o0 = Mu[X] E[p] + c,  o1 = Mu[X+1] E[p] + Mu[X+2] a1 + Mu[X+3] h,
+//   o2 = Mu[X] E[v p] + E[v] c,  o3 = Mu[X] E[w p] + E[w] c,
+//   o4 = (Mu[X+2] E[p] + Mu[X+3] a1 + Mu[X+4] h + Mu[X] E[r p] + E[r] c) / 2
+// (the assembly of the u-series (p, a1, h) with its two constant terms
+// gathered).
+template <class R, int X>
+__device__ __forceinline__ void assemble_apsi(const R a[5], const Quad<R>& qp, const VW<R>& e, const R Mu[7],
+                                              R o[5]) {
+  const R h = R(0.5) * a[4];
+  const R c = Mu[X + 1] * a[1] + Mu[X + 2] * h;
+  o[0] = Mu[X] * qp.e0 + c;
+  o[1] = Mu[X + 1] * qp.e0 + Mu[X + 2] * a[1] + Mu[X + 3] * h;
+  o[2] = Mu[X] * qp.ev + e.v * c;
+  o[3] = Mu[X] * qp.ew + e.w * c;
+  o[4] = R(0.5) * (Mu[X + 2] * qp.e0 + Mu[X + 3] * a[1] + Mu[X + 4] * h + Mu[X] * qp.er + e.r * c);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +527,7 @@ template <class R> struct GasParams {
   R K;         // internal degrees of freedom
   R K3, iK3;   // K + 3 and its reciprocal
   R mu_ref, iT_ref, mu_exp;
+  R imu_ref;   // 1/mu_ref (0 for mu_ref = 0)
   R pr_fix;    // 1/Pr - 1
 };
 
@@ -457,6 +590,18 @@ __device__ __forceinline__ R thermal_series(const Quad<R> q[NS], const R Mu[7], 
   return t;
 }
 
+// thermal() of the u^0 moment <(a . psi) psi> (the u-series (p, a1, h) of
+// assemble_apsi): the p term as in thermal_series, the constant terms
+// gathered, theta = E[r]/2 - V E[v] - W E[w] the frame's weight of the
+// unit polynomial.
+template <class R>
+__device__ __forceinline__ R thermal_apsi(const R a[5], const Quad<R>& qp, const R Mu[7], const R Tw[4], R theta,
+                                          R V, R W) {
+  const R h = R(0.5) * a[4];
+  return qp.e0 * Tw[0] + Mu[0] * (R(0.5) * qp.er - V * qp.ev - W * qp.ew) + a[1] * Tw[1] + h * Tw[2] +
+         (Mu[1] * a[1] + Mu[2] * h) * theta;
+}
+
 // Running state of one Gauss-point flux evaluation, filled in phases so that
 // the caller can reconstruct the left inputs, consume them, then the right
 // ones, keeping few values live at a time.
@@ -493,18 +638,32 @@ __device__ __forceinline__ void flux_begin(const R ql[5], const R qr[5], const G
   }
   R ir0;
   A.s0 = primitive(q0, g.gm1, ir0, A.ihl0);
-  // collision time tau = mu(T0) / p0, T0 = p0/rho0 = 1/(2 lambda0)
+  // collision time tau = mu(T0) / p0, T0 = p0/rho0 = 1/(2 lambda0); the
+  // reciprocals come from those already formed: 1/p0 = 2 lambda0 / rho0 and
+  // 1/tau = p0 / mu
   const R p0 = A.s0.rho * A.ihl0;
-  R mu = g.mu_ref;
-  if (g.mu_exp != R(0)) mu = g.mu_ref * pow(A.ihl0 * g.iT_ref, g.mu_exp);
-  const R tau = mu * pos_rcp(p0);
-  const R itau = tau > R(0) ? pos_rcp(tau) : R(0);
+  const R ip0 = R(2) * A.s0.lam * ir0;
+  R mu = g.mu_ref, imu = g.imu_ref;
+  if (g.mu_exp != R(0)) {
+    mu = g.mu_ref * pow(A.ihl0 * g.iT_ref, g.mu_exp);
+    imu = pos_rcp(mu);
+  }
+  const R tau = mu * ip0;
+  const R itau = tau > R(0) ? p0 * imu : R(0);
   time_integrals(tau, itau, dt, A.Cn, A.Cd);
   A.hu2 = R(0.5) * (A.s0.U * A.s0.U + A.s0.V * A.s0.V + A.s0.W * A.s0.W);
+  // The accumulators start at -0: -0 + x = x exactly for every x, so the
+  // compiler drops the first addition into each (from +0 it could not, as
+  // +0 + -0 = +0).
 #pragma unroll
-  for (int k = 0; k < 5; ++k) { A.Fn[k] = R(0); A.Fd[k] = R(0); A.dq0t[0][k] = R(0); A.dq0t[1][k] = R(0); }
-  A.wn = R(0);
-  A.wd = R(0);
+  for (int k = 0; k < 5; ++k) {
+    A.Fn[k] = R(-0.0);
+    A.Fd[k] = R(-0.0);
+    A.dq0t[0][k] = R(-0.0);
+    A.dq0t[1][k] = R(-0.0);
+  }
+  A.wn = R(-0.0);
+  A.wd = R(-0.0);
 }
 
 // Phase 2/3: contributions of one non-equilibrium side (g_l with u > 0 when
@@ -517,59 +676,60 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
   State<R> s = primitive(q, g.gm1, ir, ihl);
   VW<R> e;
   vw_moments(s, ihl, g.K, e);
+  // micro-slopes of the three directions: <(a_d . psi) psi> = dq_d / rho
+  const SlopeSolve<R> Sq = slope_solver(s, ihl, g.K3, g.iK3, ir);
   R a[3][5];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    R b[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = dq[d][k] * ir;
-    slope_solve(s, ihl, g.K3, g.iK3, b, a[d]);
-  }
+  for (int d = 0; d < 3; ++d) slope_solve(Sq, dq[d], a[d]);
   Quad<R> pi[4];
   series_pi(a, e, pi);
   R A[5];
   {
+    // time slope from <(A . psi) psi> = -<Pi psi>
     R Mf[7], T[5];
     chain<R, 7>(s.U, ihl, R(1), s.U, Mf);
     assemble<R, 0, 4>(pi, Mf, T);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) T[k] = -T[k];
-    slope_solve(s, ihl, g.K3, g.iK3, T, A);
+    slope_solve(slope_solver(s, ihl, g.K3, g.iK3, R(-1)), T, A);
   }
   R Mh[7];
   if (LEFT) chain<R, 7>(s.U, ihl, Acc.lm0, Acc.lm1, Mh);
   else chain<R, 7>(s.U, ihl, Acc.rm0, Acc.rm1, Mh);
   const Quad<R> unit[1] = {quad_c(R(1), e)};
-  Quad<R> qa[3];
-  series_apsi(A, e, qa);
+  const Quad<R> qA = quad_p(A, e);
   const R rho = s.rho;
   const R U0 = Acc.s0.U, V0 = Acc.s0.V, W0 = Acc.s0.W;
+  // the side's density times the time coefficients of its three terms
+  R rn[3], rd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rn[i] = rho * Acc.Cn[3 + i];
+    rd[i] = rho * Acc.Cd[3 + i];
+  }
   {
     R X1[5], X2[5], X3[5];
     assemble<R, 1, 1>(unit, Mh, X1);
     assemble<R, 1, 4>(pi, Mh, X2);
-    assemble<R, 1, 3>(qa, Mh, X3);
+    assemble_apsi<R, 1>(A, qA, e, Mh, X3);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      Acc.Fn[k] += rho * (Acc.Cn[3] * X1[k] + Acc.Cn[4] * X2[k] + Acc.Cn[5] * X3[k]);
-      Acc.Fd[k] += rho * (Acc.Cd[3] * X1[k] + Acc.Cd[4] * X2[k] + Acc.Cd[5] * X3[k]);
+      Acc.Fn[k] = ((Acc.Fn[k] + rn[0] * X1[k]) + rn[1] * X2[k]) + rn[2] * X3[k];
+      Acc.Fd[k] = ((Acc.Fd[k] + rd[0] * X1[k]) + rd[1] * X2[k]) + rd[2] * X3[k];
     }
   }
   {
     R Tw[4];
     thermal_weights(Mh, U0, Acc.hu2, Tw);
-    const R y1 = thermal_series<R, 1>(unit, Mh, Tw, V0, W0);
+    const R theta = R(0.5) * e.r - V0 * e.v - W0 * e.w;
+    const R y1 = Tw[0] + Mh[0] * theta;
     const R y2 = thermal_series<R, 4>(pi, Mh, Tw, V0, W0);
-    const R y3 = thermal_series<R, 3>(qa, Mh, Tw, V0, W0);
-    Acc.wn += rho * (Acc.Cn[3] * y1 + Acc.Cn[4] * y2 + Acc.Cn[5] * y3);
-    Acc.wd += rho * (Acc.Cd[3] * y1 + Acc.Cd[4] * y2 + Acc.Cd[5] * y3);
+    const R y3 = thermal_apsi(A, qA, Mh, Tw, theta, V0, W0);
+    Acc.wn = ((Acc.wn + rn[0] * y1) + rn[1] * y2) + rn[2] * y3;
+    Acc.wd = ((Acc.wd + rd[0] * y1) + rd[1] * y2) + rd[2] * y3;
   }
 #pragma unroll
   for (int d = 1; d < 3; ++d) {
-    Quad<R> qt[3];
-    series_apsi(a[d], e, qt);
     R t[5];
-    assemble<R, 0, 3>(qt, Mh, t);
+    assemble_apsi<R, 0>(a[d], quad_p(a[d], e), e, Mh, t);
 #pragma unroll
     for (int k = 0; k < 5; ++k) Acc.dq0t[d - 1][k] += rho * t[k];
   }
@@ -588,50 +748,44 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
   R Mf[7];
   chain<R, 7>(s0.U, ihl0, R(1), s0.U, Mf);
   R a[3][5];
-  const R ir = pos_rcp(s0.rho);
   {
-    R b[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = dq0n[k] * ir;
-    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[0]);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[0][k] * ir;
-    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[1]);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = Acc.dq0t[1][k] * ir;
-    slope_solve(s0, ihl0, g.K3, g.iK3, b, a[2]);
+    const SlopeSolve<R> Sq = slope_solver(s0, ihl0, g.K3, g.iK3, pos_rcp(s0.rho));
+    slope_solve(Sq, dq0n, a[0]);
+    slope_solve(Sq, Acc.dq0t[0], a[1]);
+    slope_solve(Sq, Acc.dq0t[1], a[2]);
   }
   Quad<R> pi[4];
   series_pi(a, e, pi);
   R T[5];  // sum_d <s_d (a_d . psi) psi>_0
   assemble<R, 0, 4>(pi, Mf, T);
   R A[5];
-  {
-    R b[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = -T[k];
-    slope_solve(s0, ihl0, g.K3, g.iK3, b, A);
-  }
+  slope_solve(slope_solver(s0, ihl0, g.K3, g.iK3, R(-1)), T, A);
   const Quad<R> unit[1] = {quad_c(R(1), e)};
-  Quad<R> qa[3];
-  series_apsi(A, e, qa);
+  const Quad<R> qA = quad_p(A, e);
   const R rho = s0.rho;
+  R rn[3], rd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rn[i] = rho * Acc.Cn[i];
+    rd[i] = rho * Acc.Cd[i];
+  }
   R X1[5], X2[5], X3[5];
   assemble<R, 1, 1>(unit, Mf, X1);
   assemble<R, 1, 4>(pi, Mf, X2);
-  assemble<R, 1, 3>(qa, Mf, X3);
+  assemble_apsi<R, 1>(A, qA, e, Mf, X3);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    Fn[k] = Acc.Fn[k] + rho * (Acc.Cn[0] * X1[k] + Acc.Cn[1] * X2[k] + Acc.Cn[2] * X3[k]);
-    Fd[k] = Acc.Fd[k] + rho * (Acc.Cd[0] * X1[k] + Acc.Cd[1] * X2[k] + Acc.Cd[2] * X3[k]);
+    Fn[k] = ((Acc.Fn[k] + rn[0] * X1[k]) + rn[1] * X2[k]) + rn[2] * X3[k];
+    Fd[k] = ((Acc.Fd[k] + rd[0] * X1[k]) + rd[1] * X2[k]) + rd[2] * X3[k];
   }
   R Tw[4];
   thermal_weights(Mf, s0.U, Acc.hu2, Tw);
-  const R y1 = thermal_series<R, 1>(unit, Mf, Tw, s0.V, s0.W);
+  const R theta = R(0.5) * e.r - s0.V * e.v - s0.W * e.w;
+  const R y1 = Tw[0] + Mf[0] * theta;
   const R y2 = thermal(T, s0.U, s0.V, s0.W, Acc.hu2);
-  const R y3 = thermal_series<R, 3>(qa, Mf, Tw, s0.V, s0.W);
-  const R wn = Acc.wn + rho * (Acc.Cn[0] * y1 + Acc.Cn[1] * y2 + Acc.Cn[2] * y3);
-  const R wd = Acc.wd + rho * (Acc.Cd[0] * y1 + Acc.Cd[1] * y2 + Acc.Cd[2] * y3);
+  const R y3 = thermal_apsi(A, qA, Mf, Tw, theta, s0.V, s0.W);
+  const R wn = ((Acc.wn + rn[0] * y1) + rn[1] * y2) + rn[2] * y3;
+  const R wd = ((Acc.wd + rd[0] * y1) + rd[1] * y2) + rd[2] * y3;
   // the heat flux is linear in the window, so the correction applies to F^n
   // and to its derivative alike
   const R qhn = thermal(Fn, s0.U, s0.V, s0.W, Acc.hu2) - s0.U * wn;
