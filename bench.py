@@ -41,9 +41,9 @@ UNIT = "cell-stage updates/s"
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
-    "sources_sha256": "71e42a8e538ac2a203b419704574e7e0b9a4062be2fed8b7eeb8a819c889cff9",
-    "fp64_flop_per_gp": 4766.3,   # FP64 flux kernel (its FP32 operations: 4 per lane)
-    "fp32_flop_per_gp": 4286.0,   # FP32 flux kernel of the mixed path (plus 42 FP64 per lane)
+    "sources_sha256": "ee74ee32dc7a0fe7f141d5ed2e88588921c03b27a133e7f01cb1b626673fc7e5",
+    "fp64_flop_per_gp": 4023.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
+    "fp32_flop_per_gp": 3743.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
 }
 # Bytes the method must move per cell-stage (FP64 state): stage 1 reads Q^n
 # and writes Q* and the S2O4 accumulator, stage 2 reads Q* and the
@@ -58,9 +58,9 @@ ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "71e42a8e538ac2a203b419704574e7e0b9a4062be2fed8b7eeb8a819c889cff9",
-    "fetch_bytes": 9.5258e+09,
-    "write_bytes": 1.5483e+09,
+    "sources_sha256": "ee74ee32dc7a0fe7f141d5ed2e88588921c03b27a133e7f01cb1b626673fc7e5",
+    "fetch_bytes": 9.5262e+09,
+    "write_bytes": 1.3527e+09,
 }
 
 # MI355X published peaks
