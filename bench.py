@@ -102,6 +102,26 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def fma_ceiling(blocks: int = 4096, iters: int = 4096, reps: int = 3) -> dict:
+    """The FP64 FMA rate this GPU sustains now (library probe: 8 independent
+    chains of dependent FMAs per lane), best of `reps` runs timed with events
+    on the stream the probe runs on."""
+    out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    hgks.hgks_fma_probe(out.data_ptr(), blocks, 16, stream)  # warm
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        hgks.hgks_fma_probe(out.data_ptr(), blocks, iters, stream)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    tflops = 16.0 * iters * blocks * 256 / best / 1e12
+    return {"achieved": round(tflops, 2), "unit": "TFLOP/s", "frac_of_peak": round(tflops / PEAK_FP64_VECTOR_TFLOPS, 4),
+            "probe": f"{blocks} x 256 threads, 8 independent chains of {iters} FP64 FMAs per thread"}
+
+
 def ensemble_bench(steps: int, precision: str) -> dict:
     """64 TGV instances, N from {24, 32, 48, 64, 96}, Ma ~ U[0.1, 0.5], Re ~
     U[400, 3000] (seeded): one batched context (persistent tile launches,
@@ -512,6 +532,10 @@ def main() -> int:
         return elapsed, roofline, st, state, spread
 
     elapsed, roofline, st, state64, spread = run("fp64")
+    # the FP64 FMA rate the GPU sustains (clock and issue under FP64 load), as
+    # the ceiling beside the published peak
+    roofline["sustained_fp64_fma"] = fma_ceiling()
+    roofline["frac_of_sustained_fma"] = round(roofline["achieved"] / roofline["sustained_fp64_fma"]["achieved"], 4)
     cell_stages = 2.0 * n ** 3 * args.steps
     value = cell_stages / elapsed
     out = {

@@ -190,6 +190,16 @@ hgks_status hgks_residual_static(const hgks_config* cfg, const double* q_dev, do
 hgks_status hgks_profile(hgks_ctx ctx, int32_t enable);
 hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int64_t launches[HGKS_PROFILE_CLASSES]);
 
+/* Measurement aid for roofline figures, not a step of the method: the FP64
+ * FMA rate this GPU sustains now.  Launches blocks x 256 threads on hip_stream
+ * (NULL: the default stream); each thread runs 8 independent chains of iters
+ * dependent FP64 FMAs (16 iters operations per thread) and writes the sum of
+ * its chains to out_dev[block * 256 + thread] (caller-owned device memory of
+ * blocks * 256 doubles).  Asynchronous; time it with events on the same
+ * stream.  Errors: HGKS_E_INVALID (null out_dev, blocks or iters not
+ * positive), HGKS_E_DEVICE. */
+hgks_status hgks_fma_probe(double* out_dev, int32_t blocks, int32_t iters, void* hip_stream);
+
 /* ---- Batched ensemble ----------------------------------------------------
  * Many independent instances (each its own grid size, gas and state) advanced
  * together: every phase of a step is one launch over the concatenated tile

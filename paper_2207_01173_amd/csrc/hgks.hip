@@ -2129,6 +2129,21 @@ static hgks_status batch_init_body(hgks_ctx b, int n, const hgks_config* cfgs, d
   return HGKS_OK;
 }
 
+// FP64 FMA issue-rate probe: 8 independent chains of dependent FMAs per lane.
+__global__ __launch_bounds__(256) void fma_probe_kernel(double* __restrict__ out, int iters) {
+  double x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = 1.0 + 1e-3 * threadIdx.x + j;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = fma(x[j], 0.999999, 1e-7);
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sum += x[j];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = sum;
+}
+
 extern "C" {
 
 hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes) {
@@ -2383,6 +2398,12 @@ hgks_status hgks_profile_read(hgks_ctx ctx, double ms[HGKS_PROFILE_CLASSES], int
   }
   ctx->ev_used = 0;
   return HGKS_OK;
+}
+
+hgks_status hgks_fma_probe(double* out_dev, int32_t blocks, int32_t iters, void* hip_stream) {
+  if (!out_dev || blocks <= 0 || iters <= 0) return HGKS_E_INVALID;
+  hipLaunchKernelGGL(fma_probe_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, out_dev, iters);
+  return hipGetLastError() == hipSuccess ? HGKS_OK : HGKS_E_DEVICE;
 }
 
 hgks_status hgks_destroy(hgks_ctx ctx) {

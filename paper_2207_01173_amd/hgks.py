@@ -25,7 +25,7 @@ EXPORTED = [
     "hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
     "hgks_destroy", "hgks_status_string", "hgks_last_error", "hgks_profile", "hgks_profile_read",
     "hgks_batch_workspace_size", "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info",
-    "hgks_residual_static",
+    "hgks_residual_static", "hgks_fma_probe",
 ]
 STATIC_SCRATCH_BYTES = 64 << 20
 PROFILE_CLASSES = ("recon", "flux", "update", "other")
@@ -97,6 +97,7 @@ def lib():
         L.hgks_dt.argtypes = [vp, ctypes.POINTER(d)]
         L.hgks_residual.argtypes = [vp, vp, d, vp, vp]
         L.hgks_residual_static.argtypes = [C, vp, d, vp, vp, vp]
+        L.hgks_fma_probe.argtypes = [vp, i32, i32, vp]
         L.hgks_destroy.argtypes = [vp]
         L.hgks_batch_workspace_size.argtypes = [i32, C, ctypes.POINTER(sz)]
         L.hgks_batch_init.argtypes = [i32, C, ctypes.POINTER(vp), vp, sz, vp, ctypes.POINTER(vp)]
@@ -110,7 +111,7 @@ def lib():
         L.hgks_last_error.argtypes = [vp]
         L.hgks_last_error.restype = ctypes.c_char_p
         for f in ("hgks_workspace_size", "hgks_init", "hgks_step", "hgks_stats", "hgks_dt", "hgks_residual",
-                  "hgks_residual_static",
+                  "hgks_residual_static", "hgks_fma_probe",
                   "hgks_destroy", "hgks_profile", "hgks_profile_read", "hgks_batch_workspace_size",
                   "hgks_batch_init", "hgks_batch_step", "hgks_batch_stats", "hgks_batch_info"):
             getattr(L, f).restype = i32
@@ -199,6 +200,12 @@ def hgks_residual_static(cfg, q_ptr: int, dt: float, L_ptr: int, dL_ptr: int, st
                                 ctypes.c_void_p(dL_ptr), ctypes.c_void_p(stream_ptr))
     if st != HGKS_OK:
         raise HGKSError(st, L.hgks_last_error(None).decode())
+
+
+def hgks_fma_probe(out_ptr: int, blocks: int, iters: int, stream_ptr: int):
+    """Enqueue the FP64 FMA-rate probe (16 * iters operations per thread,
+    blocks * 256 threads) on the stream."""
+    _check(lib().hgks_fma_probe(ctypes.c_void_p(out_ptr), int(blocks), int(iters), ctypes.c_void_p(stream_ptr)), None)
 
 
 def hgks_profile(ctx, enable: bool):
