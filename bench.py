@@ -106,6 +106,10 @@ def fma_ceiling(blocks: int = 4096, iters: int = 4096, reps: int = 3) -> dict:
     """The FP64 FMA rate this GPU sustains now (library probe: 8 independent
     chains of dependent FMAs per lane), best of `reps` runs timed with events
     on the stream the probe runs on."""
+    import torch
+
+    from paper_2207_01173_amd import hgks
+
     out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
     hgks.hgks_fma_probe(out.data_ptr(), blocks, 16, stream)  # warm
