@@ -36,8 +36,9 @@ UNIT = "cell-stage updates/s"
 # whole dispatches of the 256^3 TGV: 64 x (ADD + MUL + TRANS + 2 FMA) per wave
 # instruction, divided by the lanes the dispatch launched
 # (profiles/flux_executed_flops_tgv256.md; tests/test_bench_constants.py keeps
-# the two in step).  The roofline credits only the lanes of real faces (4 per
-# face), so the padded lanes of ragged tiles count for nothing.  Valid for the
+# the two in step).  The roofline credits only the lanes of distinct faces (4
+# per face, n^3 faces per direction on the periodic box), so the padded lanes
+# of ragged tiles count for nothing.  Valid for the
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
@@ -485,7 +486,7 @@ def main() -> int:
         if st["nonfinite"] or not (st["min_p"] > 0):
             raise RuntimeError(f"{prec_name}: state became invalid during the benchmark")
         flux_ms, flux_n = prof["flux"]
-        faces_per_launch = (n + 1) * n * n
+        faces_per_launch = n * n * n  # every axis periodic: n distinct faces along each normal
         launch_s = flux_ms / flux_n / 1e3
         fp64 = prec == hgks.FP64
         flop_per_gp = FLUX_EXECUTED["fp64_flop_per_gp" if fp64 else "fp32_flop_per_gp"]

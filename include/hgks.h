@@ -115,10 +115,11 @@ typedef struct {
 /* Workspace bytes for a configuration.  Errors: HGKS_E_INVALID, also for a
  * grid too large for the kernels' 32-bit offsets into the face buffer: for
  * each face direction, with (e_x, e_y, e_z) that direction's face extents
- * (n + 1 along the normal, n elsewhere, plus 2 ghost faces on each side of a
- * wall axis when it is the second tangential one) and pitch = e_x rounded up
- * to 32, 16 x pitch x e_y x (e_z + 1) bytes must stay below 2^32 (a 630^3
- * grid is accepted, 640^3 is not). */
+ * (n along a periodic normal, whose face n is face 0, n + 1 along a wall
+ * normal, n elsewhere, plus 2 ghost faces on each side of a wall axis when it
+ * is the second tangential one) and pitch = e_x rounded up to 32,
+ * 16 x pitch x e_y x (e_z + 1) bytes must stay below 2^32 (a periodic 640^3
+ * grid is accepted, 641^3 is not). */
 hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes);
 
 /* Create a context over caller-owned memory: q_dev (state, in/out), ws_dev
@@ -171,9 +172,10 @@ hgks_status hgks_residual(hgks_ctx ctx, const double* q_dev, double dt, double* 
  * Errors (the detail text of the calling thread's last failure:
  * hgks_last_error(NULL)): HGKS_E_INVALID for an invalid configuration, a null
  * or misaligned pointer or dt not positive and finite; HGKS_E_UNSUPPORTED for
- * a grid whose face buffers exceed the static array (a cube of up to 35^3
- * cells fits in FP64, 44^3 with the FP32 face data of the mixed and FP32
- * precisions); HGKS_E_DEVICE for a HIP error. */
+ * a grid whose face buffers exceed the static array (a periodic cube of up to
+ * 36^3 cells fits in FP64, 34^3 with walls on y; 44^3 and 43^3 with the FP32
+ * face data of the mixed and FP32 precisions); HGKS_E_DEVICE for a HIP
+ * error. */
 #define HGKS_STATIC_SCRATCH_BYTES (64u << 20)
 hgks_status hgks_residual_static(const hgks_config* cfg, const double* q_dev, double dt, double* L_dev,
                                  double* dL_dev, void* hip_stream);

@@ -82,14 +82,17 @@ __host__ __device__ inline size_t cells(const Params& P) { return (size_t)P.n[0]
 // Face extents of direction d: one more face than cells along d (on a
 // periodic axis the last face repeats face 0 and is computed from the same
 // data).
+// Faces of direction d per axis: n along the tangential axes; along the
+// normal n + 1 on a wall axis and n on a periodic one, where face n is face 0
+// (the same stencil after the wrap, so the same flux): the update reads face
+// 0 as the last cell's right face.
 __host__ __device__ inline void face_extents(const Params& P, int d, int fe[3]) {
-  for (int a = 0; a < 3; ++a) fe[a] = P.n[a] + (a == d ? 1 : 0);
+  for (int a = 0; a < 3; ++a) fe[a] = P.n[a] + (a == d && P.bc[d] != HGKS_BC_PERIODIC ? 1 : 0);
 }
 
 // Row pitch of the face arrays (buffer B and the face fluxes F): the x extent
 // rounded up to 32 elements, so that every row starts on a 128-byte boundary
-// and a tile's 16-face rows do not straddle cache lines (direction x has n + 1
-// faces along x).
+// and a tile's 16-face rows do not straddle cache lines.
 __host__ __device__ inline int face_pitch(int nx) { return (nx + 31) & ~31; }
 
 // Tile order across the grid of blocks: tile index `fast` varies fastest
@@ -992,7 +995,9 @@ __device__ __forceinline__ void cell_residual(const S* __restrict__ qe, const do
     const size_t NF = (size_t)fpitch * fe[1] * fe[2];
     const size_t fm = ((size_t)k * fe[1] + j) * fpitch + i;
     const size_t step = d == 0 ? 1 : (d == 1 ? (size_t)fpitch : (size_t)fpitch * fe[1]);
-    const size_t fp = fm + step;
+    // right face; on a periodic normal axis the last cell's is face 0
+    const int ci = d == 0 ? i : (d == 1 ? j : k);
+    const size_t fp = fe[d] == P.n[d] && ci == P.n[d] - 1 ? fm - (size_t)ci * step : fm + step;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       L[m] -= (Fd[d][m * NF + fp] - Fd[d][m * NF + fm]) / vol;

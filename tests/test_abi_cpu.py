@@ -91,17 +91,21 @@ def test_status_strings():
 def test_largest_grids():
     """The flux kernel's 32-bit lane offsets into buffer B span one quantity
     (both Gauss lines), the next quantity's offset and one z plane:
-    2 x 8 x pitch(n_x + 1) x n_y x (n_z + 1) must stay below 2^32 (pitch = x
-    extent rounded up to 32).  630^3 fits (640 x 630 x 631), 640^3 does not
-    (672 x 640 x 641); 512^3 is well inside."""
-    for n, ok in ((512, True), (630, True), (640, False)):
-        c = hgks.make_config(W.tgv_params(n))
-        if ok:
-            assert hgks.hgks_workspace_size(c) > 0
-        else:
-            with pytest.raises(hgks.HGKSError) as e:
-                hgks.hgks_workspace_size(c)
-            assert e.value.status == hgks.HGKS_E_INVALID
+    2 x 8 x pitch(e_x) x e_y x (e_z + 1) must stay below 2^32 for every face
+    direction (pitch = x extent rounded up to 32; a periodic normal axis holds
+    n faces, face n being face 0).  A periodic 640^3 grid fits (640 x 640 x
+    641 for each direction), 641^3 does not (672 x 641 x 642); with walls on y
+    (y faces: 640 x 641 x 641; z faces with 4 ghost rows along y: 640 x 644 x
+    641) 640^3 fits too and 641^3 does not; 512^3 and 630^3 are inside."""
+    for make in (W.tgv_params, lambda n: W.channel_params((n, n, n))):
+        for n, ok in ((512, True), (630, True), (640, True), (641, False)):
+            c = hgks.make_config(make(n))
+            if ok:
+                assert hgks.hgks_workspace_size(c) > 0
+            else:
+                with pytest.raises(hgks.HGKSError) as e:
+                    hgks.hgks_workspace_size(c)
+                assert e.value.status == hgks.HGKS_E_INVALID
 
 
 def test_batch_rejects_unsupported_members():

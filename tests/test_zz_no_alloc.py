@@ -84,9 +84,9 @@ def test_static_residual_matches_context_residual(hg, precision):
 def test_static_residual_size_limit(hg):
     import torch
 
-    p = W.tgv_params(36)  # 36^3 FP64 face buffers exceed the static array
+    p = W.tgv_params(37)  # 37^3 FP64 face buffers exceed the static array (36^3 fits)
     cfg = hg.make_config(p)
-    q = torch.ones((5, 36, 36, 36), dtype=torch.float64, device="cuda")
+    q = torch.ones((5, 37, 37, 37), dtype=torch.float64, device="cuda")
     with pytest.raises(hg.HGKSError) as e:
         hg.hgks_residual_static(cfg, q.data_ptr(), 1e-3, q.data_ptr(), q.data_ptr(), 0)
     assert e.value.status == hg.HGKS_E_UNSUPPORTED
