@@ -955,6 +955,116 @@ __device__ __forceinline__ void flux_tile4(const double* __restrict__ B, const P
                                              reinterpret_cast<double*>(&stage[0][0][0]));
 }
 
+// ---- FP64 flux tiles of y faces with the t2 stencils shared in LDS ---------
+// For y faces t2 is x.  A flux block takes 16 faces along x at 4 consecutive
+// z positions (t1; wave w holds position w); the t2 stencils of a row span its
+// 20 faces x0 - 2 .. x0 + 17 (x wraps: it is never a wall axis).  At its start
+// the block copies the 35 quantities of its 4 rows into LDS, 32 entries per
+// row so that, as for the x and z faces, one lane address serves every copy
+// (entries 20..31 repeat entry 19 and are never read).
+constexpr int FLUX4Y_Z = 4, FLUX4Y_W = 32;
+__host__ __device__ inline void flux4y_tile_counts(const Params& P, int nt[3]) {
+  int fe[3];
+  face_extents(P, 1, fe);
+  nt[0] = (fe[0] + FLUX4_X - 1) / FLUX4_X;
+  nt[1] = fe[1];
+  nt[2] = (fe[2] + FLUX4Y_Z - 1) / FLUX4Y_Z;
+}
+__host__ __device__ inline int flux4y_tiles(const Params& P) {
+  int nt[3];
+  flux4y_tile_counts(P, nt);
+  return nt[0] * nt[1] * nt[2];
+}
+
+__device__ __forceinline__ void flux_tile4y(const double* __restrict__ B, const Params& P,
+                                            const double* __restrict__ qref, double dt, double* __restrict__ F,
+                                            int lin) {
+  constexpr int DIR = 1, D1 = 2, D2 = 0;
+  int fe[3], be[3], bo[3];
+  face_extents(P, DIR, fe);
+  b_extents(P, DIR, be, bo);
+  int nt[3], tc[3];
+  flux4y_tile_counts(P, nt);
+  tile_coords(lin, nt, 0, tc);  // x tiles adjacent: neighbours share their halo faces
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int f[3];
+  f[0] = tc[0] * FLUX4_X + (lane & 15);
+  f[1] = tc[1];
+  f[2] = tc[2] * FLUX4Y_Z + w;
+  const int gpi = (lane >> 4) & 3;
+  const int g1 = gpi >> 1, g2 = gpi & 1;
+  const bool valid = f[0] < fe[0] && f[2] < fe[2];
+  if (!valid) {  // keep the lane for the exchanges, on a real face
+    f[0] = min(f[0], fe[0] - 1);
+    f[2] = min(f[2], fe[2] - 1);
+  }
+
+  // Staged rows: [quantity][row][entry] of 16-byte entries (a face's two Gauss
+  // lines), row r holding z = first position + r (clamped to the last face
+  // for the rows past the grid, which only lanes past its end read) and entry
+  // i the face x = x0 - 2 + min(i, 19).  Entry e = (q FLUX4Y_Z + r) FLUX4Y_W
+  // + i; thread tid copies entries tid + 256 k: row and entry do not depend on
+  // k and the quantity is 2 k + tid / 128.
+  __shared__ double2 stage[B_COUNT][FLUX4Y_Z][FLUX4Y_W];
+  constexpr int kEntries = B_COUNT * FLUX4Y_Z * FLUX4Y_W;
+  {
+    const int r = (tid >> 5) & (FLUX4Y_Z - 1), ei = tid & (FLUX4Y_W - 1);
+    int x = tc[0] * FLUX4_X - 2 + min(ei, FLUX4_X + 3);
+    x = ((x % P.n[0]) + P.n[0]) % P.n[0];
+    int b[3];
+    b[0] = x;
+    b[1] = f[1];
+    b[2] = min(tc[2] * FLUX4Y_Z + r, fe[2] - 1);
+    const HGKS_GLOBAL char* lane_src =
+        reinterpret_cast<const HGKS_GLOBAL char*>(gmem(B)) +
+        (b64_face(b[0] - bo[0], b[1] - bo[1], b[2] - bo[2], face_pitch(be[0]), be[1]) + (size_t)(tid >> 7) * 32) *
+            sizeof(double);
+#pragma unroll
+    for (int k = 0; k < (kEntries + FLUX_THREADS - 1) / FLUX_THREADS; ++k)
+      if (FLUX_THREADS * k + 64 * w < kEntries)  // wave-uniform
+        dma16_to_lds(lane_src + (size_t)(2 * k) * 32 * sizeof(double),
+                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * w));
+  }
+  double sn = gmem(P.dface[DIR])[f[DIR]];
+  double st1 = gmem(P.dgp[D1])[2 * f[D1] + g1];
+  double st2 = gmem(P.dgp[D2])[2 * f[D2] + g2];
+  const HGKS_GLOBAL double* qrg = gmem(qref);
+  double rl[5];
+  rl[0] = qrg[0];
+  rl[1] = qrg[1 + DIR];
+  rl[2] = qrg[1 + D1];
+  rl[3] = qrg[1 + D2];
+  rl[4] = qrg[4];
+  wait_vmem();      // this wave's copies and loads have landed
+  __syncthreads();  // and every wave's
+  const double* const st = reinterpret_cast<const double*>(&stage[0][0][0]);
+  const int base = (w * FLUX4Y_W + (lane & 15)) * 2 + g1;  // quantity 0, row w, stencil entry 0, line g1
+  auto begin = [&](int p) {
+    // phase 1's quantities are read by then; their space takes the carried values
+    if (p == 1) __syncthreads();
+  };
+  auto pair = [&](int qi0, double v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = st[base + ((qi0 + g2) * FLUX4Y_Z * FLUX4Y_W + j) * 2];
+  };
+  auto plain = [&](int qi, double v[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = st[base + (qi * FLUX4Y_Z * FLUX4Y_W + j) * 2];
+  };
+  static_assert(10 * FLUX4Y_Z * FLUX4Y_W * 2 >= 7 * FLUX_THREADS, "phase 1's quantities hold the carried values");
+  flux_lane<DIR, double, FLUX_THREADS, true>(begin, pair, plain, P, dt, F, f, valid, gpi, sn, st1, st2, rl,
+                                             reinterpret_cast<double*>(&stage[0][0][0]));
+}
+
+__global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux4y_kernel(const double* __restrict__ B, Params P,
+                                                                              const double* __restrict__ qref,
+                                                                              const Scalars* __restrict__ sc,
+                                                                              int use_residual_dt,
+                                                                              double* __restrict__ F) {
+  const double dt = use_residual_dt ? sc->dt_residual : sc->dt;
+  flux_tile4y(B, P, qref, dt, F, xcd_linear_block(flux4y_tiles(P)));
+}
+
 template <int DIR>
 __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux4_kernel(const double* __restrict__ B, Params P,
                                                                              const double* __restrict__ qref,
@@ -1340,6 +1450,8 @@ __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_batch_kern
   const BatchEntry& e = T.E[find_instance(T, flux_row<TX>(DIR), t, local)];
   if constexpr (sizeof(R) == 8 && DIR != 1)  // the tiles of a standalone run of the member
     flux_tile4<DIR>(static_cast<const double*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
+  else if constexpr (sizeof(R) == 8)
+    flux_tile4y(static_cast<const double*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
   else
     flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
 }
@@ -1700,6 +1812,9 @@ static void launch_flux(const Params& P, hipStream_t stream, const R* B, const d
   if constexpr (sizeof(R) == 8 && D != 1)
     hipLaunchKernelGGL((flux4_kernel<D>), dim3((unsigned)flux4_tiles(P, D)), dim3(FLUX_THREADS), 0, stream, B, P,
                        qref, sc, use_residual_dt, F);
+  else if constexpr (sizeof(R) == 8)
+    hipLaunchKernelGGL(flux4y_kernel, dim3((unsigned)flux4y_tiles(P)), dim3(FLUX_THREADS), 0, stream, B, P, qref, sc,
+                       use_residual_dt, F);
   else
     hipLaunchKernelGGL((flux_kernel<D, R>), dim3((unsigned)flux_tiles<16>(P, D)), dim3(FLUX_THREADS), 0, stream, B,
                        P, qref, sc, use_residual_dt, F);
@@ -1833,10 +1948,10 @@ static std::vector<int> batch_prefix(int n, const hgks_config* cfgs) {
     items[PRE_RECON + 1] = f32 ? recon_tiles<1, float>(P) : recon_tiles<1, double>(P);
     items[PRE_RECON + 2] = f32 ? recon_tiles<2, float>(P) : recon_tiles<2, double>(P);
     for (int d = 0; d < 3; ++d) {
-      // FP64 x and z faces: the 4-position tiles whatever the width
-      const bool four = !f32 && d != 1;
-      items[flux_row<16>(d)] = four ? flux4_tiles(P, d) : flux_tiles<16>(P, d);
-      items[flux_row<32>(d)] = four ? flux4_tiles(P, d) : flux_tiles<32>(P, d);
+      // FP64: the staged 4-position tiles whatever the width
+      const long long four = d == 1 ? flux4y_tiles(P) : flux4_tiles(P, d);
+      items[flux_row<16>(d)] = f32 ? flux_tiles<16>(P, d) : four;
+      items[flux_row<32>(d)] = f32 ? flux_tiles<32>(P, d) : four;
     }
     items[PRE_CELL] = (long long)((cells(P) + CELL_THREADS - 1) / CELL_THREADS);
     for (int r = 0; r < PRE_ROWS; ++r) {
