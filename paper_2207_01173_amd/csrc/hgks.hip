@@ -4,9 +4,11 @@
 //   recon_kernel<d>: normal WENO-Z sweep of a face tile (values and slopes of
 //     the left/right states and the equilibrium slope), staged in LDS, then
 //     the first tangential sweep to the two Gauss lines along t1 -> buffer B.
-//   flux_kernel<d>:  one lane per Gauss point: second tangential sweep along t2,
+//   flux4_kernel<d> (FP64 x and z faces), flux4y_kernel (FP64 y faces),
+//   flux_kernel<d> (FP32 face data): one lane per Gauss point: second
+//     tangential sweep along t2 (the FP64 kernels from B rows staged in LDS),
 //     the BGK flux of Eq. (flux) integrated over [0, dt] and [0, dt/2], the
-//     2x2 Gauss sum by cross-lane shuffles, F^n and dF^n/dt -> face buffer F_d.
+//     2x2 Gauss sum by cross-lane swaps, F^n and dF^n/dt -> face buffer F_d.
 // then update_kernel<stage>: L, dL/dt from the six faces of each cell and the
 // two-stage update of Eq. (two-stage); stage 2 also reduces the wave speed of
 // the new state for the next CFL time step.
@@ -485,9 +487,10 @@ __device__ __forceinline__ void gauss_sum_store(const Params& P, double* __restr
 }
 
 constexpr int FLUX_THREADS = 256;  // 64 faces x 4 Gauss points
-// At least two blocks (two waves per SIMD) resident per CU: the FP64 kernel is
-// held to 256 registers per lane, spilling a few phase-1 values that only
-// phase 4 reads, so that a second wave hides each phase's load latency.
+// At least two blocks (two waves per SIMD) resident per CU: the FP64 kernels
+// fit 256 registers per lane without spills (the values that phase 4 needs
+// from phase 1 wait in LDS), and the second wave hides each phase's LDS and
+// memory latency.
 constexpr int FLUX_MIN_BLOCKS = 2;
 
 // Flux tiles: 64 faces, TX along x times 64/TX along y, one z plane.
@@ -504,13 +507,11 @@ template <int TX> __host__ __device__ inline int flux_tiles(const Params& P, int
   return nt[0] * nt[1] * nt[2];
 }
 
-// Second tangential sweep, Gauss-point flux, Gauss sum, F^n and dF^n/dt for
-// flux tile `lin` of direction DIR.  Lane layout in a wavefront: lanes
-// 16 g .. 16 g + 15 hold Gauss point g of 16 consecutive faces along x; the
-// four waves of the block take four 16-face groups of the TX x (64/TX) tile.
-// The flux of one lane's Gauss point and the face's 2x2 Gauss sum (the phases
-// of flux_tile below, with the stencils from a caller-given source), for the
-// staged tiles of flux_tile4.  The source: begin(p) at the start of phase p (0..3), pair(qi0, v)
+// The flux of one lane's Gauss point and the face's 2x2 Gauss sum, in four
+// phases, for the staged FP64 tiles (flux_tile4, flux_tile4y).  Lane layout
+// in a wavefront: lanes 16 g .. 16 g + 15 hold Gauss point g of 16
+// consecutive faces along x.  The stencils come from a caller-given source:
+// begin(p) at the start of phase p (0..3), pair(qi0, v)
 // the five stencil values of quantity qi0 + g2 (Gauss-point pairs: see below),
 // plain(qi, v) those of quantity qi.  f is the lane's face (clamped to a real
 // one for the lanes beyond the grid, valid false), sn, st1, st2 the metric
@@ -640,9 +641,14 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
   gauss_sum_store<DIR>(P, F, f, valid, gpi, Fn, Fd);
 }
 
+// Second tangential sweep, Gauss-point flux, Gauss sum, F^n and dF^n/dt for
+// flux tile `lin` of direction DIR, FP32 face data: the phases of flux_lane
+// with the stencils read straight from B.  Lane layout as there; the four
+// waves of the block take four 16-face groups of the TX x (64/TX) tile.
 template <int DIR, class R, int TX>
 __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params& P, const double* __restrict__ qref,
                                           double dt, double* __restrict__ F, int lin) {
+  static_assert(sizeof(R) == 4, "FP64 face data use the staged tiles (flux_tile4, flux_tile4y)");
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
   constexpr int GX = TX / 16;  // 16-face groups along x per tile row
   int fe[3], be[3], bo[3];
@@ -669,42 +675,29 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   const int bp = face_pitch(be[0]);
   const size_t NB = (size_t)bp * be[1] * be[2];
   const size_t qstride = 2 * NB;
-  // Addressing of B: a load is a wave-uniform base held in scalar registers
-  // plus a 32-bit lane offset.  FP64 (tile-major): the base is quantity qi's
-  // place in the row (z, y) of the stencil row j, the lane offset the face's
-  // 16-face chunk and place in it, and for the Gauss-point pairs the partner
-  // quantity (one quantity, 32 doubles, further).  FP32 (quantity planes):
-  // every face of a block lies in one z plane of B for each stencil row j (z
-  // is the normal for y and z faces, and t2 for x faces, whose z then depends
-  // on j only), so the base is the quantity's start plus that plane's
-  // offset and the lane offset the face's place in the plane, plus the
-  // partner quantity's plane for the pairs (the lane offsets stay below
-  // 2^32, checked when the configuration is validated).
+  // Addressing of B (quantity planes): a load is a wave-uniform base held in
+  // scalar registers plus a 32-bit lane offset.  Every face of a block lies
+  // in one z plane of B for each stencil row j (z is the normal for y and z
+  // faces, and t2 for x faces, whose z then depends on j only), so the base
+  // is the quantity's start plus that plane's offset and the lane offset the
+  // face's place in the plane, plus the partner quantity's plane for the
+  // Gauss-point pairs (the lane offsets stay below 2^32, checked when the
+  // configuration is validated).
   const size_t plane = (size_t)bp * be[1];
-  // FP64 (tile-major B): the next quantity is 32 doubles further, the base of
-  // a stencil row is its (z, y) row of chunks (wave-uniform: one y per wave),
-  // the lane offset the face's chunk and place in it.
-  constexpr bool kTile = B_INTERLEAVED<R>;
-  const uint32_t pair_off = kTile ? 32u * sizeof(R) : second_pair_offset<R>(NB);
-  const size_t qbytes = kTile ? 32 * sizeof(R) : qstride * sizeof(R);
+  const uint32_t pair_off = second_pair_offset<R>(NB);
+  const size_t qbytes = qstride * sizeof(R);
   const bool second = g2 != 0;
   uint32_t off[5];     // lane offsets, pair partner included on the g2 = 1 lanes
-  size_t zoff[5];      // byte offsets of the stencil rows (block-uniform z plane; FP64: wave-uniform row)
+  size_t zoff[5];      // byte offsets of the stencil rows (block-uniform z plane)
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     int b[3] = {f[0], f[1], f[2]};
     int t = f[D2] + j - 2;
     if (P.bc[D2] != HGKS_BC_ISOTHERMAL_WALL) t = t < 0 ? t + P.n[D2] : (t >= P.n[D2] ? t - P.n[D2] : t);
     b[D2] = t;
-    if constexpr (kTile) {
-      zoff[j] = sizeof(R) * b64_face(0, b[1] - bo[1], b[2] - bo[2], bp, be[1]);
-      off[j] = (uint32_t)sizeof(R) * (uint32_t)(b64_face(b[0] - bo[0], 0, 0, bp, be[1]) + g1) +
-               (second ? pair_off : 0u);
-    } else {
-      zoff[j] = sizeof(R) * b_pos<R>((size_t)(b[2] - bo[2]) * plane, 0, NB);
-      const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
-      off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
-    }
+    zoff[j] = sizeof(R) * b_pos<R>((size_t)(b[2] - bo[2]) * plane, 0, NB);
+    const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
+    off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
   }
   GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
@@ -771,24 +764,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   }
   FluxAcc<R> acc;
   flux_begin(ql, qr, g, R(dt), acc);
-  // FP64: the equilibrium part's time coefficients and 1/(2 lambda0) are made
-  // in phase 1 and read only in phase 4.  They wait in LDS (one slot per
-  // lane) instead of occupying registers through the two side phases, where
-  // the compiler would otherwise spill them to scratch memory (16-60 bytes
-  // per lane; reloads wait on the vector-memory counter).  The empty asm with
-  // a memory clobber keeps the stores and the reloads apart, so the values
-  // really leave the registers.
-  constexpr bool kCarry = sizeof(R) == 8;
-  __shared__ double carry_lds[kCarry ? 7 : 1][kCarry ? FLUX_THREADS : 1];
-  if constexpr (kCarry) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      carry_lds[i][tid] = acc.Cn[i];
-      carry_lds[3 + i][tid] = acc.Cd[i];
-    }
-    carry_lds[6][tid] = acc.ihl0;
-    asm volatile("" ::: "memory");
-  }
 
   // phase 2: left side
   {
@@ -831,15 +806,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
       stencil(b_d0(k), pa[k]);
       dq0n[k] = gauss_linear(pa[k], gp) * sn;
     }
-    if constexpr (kCarry) {
-      asm volatile("" ::: "memory");
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        acc.Cn[i] = carry_lds[i][tid];
-        acc.Cd[i] = carry_lds[3 + i][tid];
-      }
-      acc.ihl0 = carry_lds[6][tid];
-    }
     flux_finish(dq0n, g, acc, Fn, Fd);
   }
 
@@ -853,8 +819,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
 // copies all 35 quantities of those rows into LDS (asynchronous global -> LDS
 // loads, 16 bytes per lane: one face's two Gauss lines; 70 KB), then every
 // phase reads its stencils from there; the other block on the CU computes
-// meanwhile.  y faces keep flux_tile: their t2 is x, whose five stencil rows
-// are shifts of the run of faces that a wave already reads together.
+// meanwhile.  y faces: flux_tile4y below.
 constexpr int FLUX4_X = 16, FLUX4_P = 4, FLUX4_ROWS = FLUX4_P + 4;
 __host__ __device__ inline void flux4_tile_counts(const Params& P, int d, int nt[3]) {
   int fe[3];
