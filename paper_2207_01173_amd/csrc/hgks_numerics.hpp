@@ -224,28 +224,50 @@ __device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp)
 // value v2 + b_k/2 + c_k/12 = v2 + tb_k/4 + c_k/12, slope b_k + c_k/2 =
 // (tb_k + c_k)/2.
 template <class R>
-__device__ __forceinline__ void face_value_slope(const R v[5], R& val, R& der) {
-  const Candidates<R> k = candidates(v);
+__device__ __forceinline__ void face_value_slope(const Candidates<R>& k, R v2, R& val, R& der) {
   R e[3], a[3];
   wz_factors(k.be, e);
   const R inv = wz_alpha(e, R(0.1), R(0.6), R(0.3), a);
   const R twelfth = R(1.0 / 12.0);
-  val = v[2] + inv * wz_dot(a, R(0.25) * k.tb[0] + twelfth * k.c[0], R(0.25) * k.tb[1] + twelfth * k.c[1],
-                            R(0.25) * k.tb[2] + twelfth * k.c[2]);
+  val = v2 + inv * wz_dot(a, R(0.25) * k.tb[0] + twelfth * k.c[0], R(0.25) * k.tb[1] + twelfth * k.c[1],
+                          R(0.25) * k.tb[2] + twelfth * k.c[2]);
   der = (R(0.5) * inv) * wz_dot(a, k.tb[0] + k.c[0], k.tb[1] + k.c[1], k.tb[2] + k.c[2]);
 }
 
 // Normal sweep at face i+1/2 from c[0..5] = Q_{i-2..i+3}: left/right values and
 // slopes, and the equilibrium slope (Q_{i-1} - 15 Q_i + 15 Q_{i+1} - Q_{i+2})/12.
+// The left state's stencil is (c0, ..., c4), the right state's the mirrored
+// (c5, ..., c1): with the first differences e_j = c_{j+1} - c_j the right
+// stencil's differences are (-e4, -e3, -e2, -e1), so the two candidate sets
+// share four differences and two second differences (c_1 and c_2 swapped),
+// each formed once (the same values, bit for bit, as from each stencil alone).
 template <class R>
 __device__ __forceinline__ void normal_sweep(const R c[6], R& ql, R& qr, R& dl, R& dr, R& d0) {
-  R vl[5] = {c[0], c[1], c[2], c[3], c[4]};
-  face_value_slope(vl, ql, dl);
-  R vr[5] = {c[5], c[4], c[3], c[2], c[1]};
+  const R e0 = c[1] - c[0], e1 = c[2] - c[1], e2 = c[3] - c[2], e3 = c[4] - c[3], e4 = c[5] - c[4];
+  Candidates<R> kl, kr;
+  kl.c[0] = e1 - e0;
+  kl.c[1] = e2 - e1;
+  kl.c[2] = e3 - e2;
+  kl.tb[0] = R(2) * e1 + kl.c[0];
+  kl.tb[1] = e1 + e2;
+  kl.tb[2] = R(2) * e2 - kl.c[2];
+  kr.c[0] = e4 - e3;
+  kr.c[1] = kl.c[2];
+  kr.c[2] = kl.c[1];
+  kr.tb[0] = R(-2) * e3 + kr.c[0];
+  kr.tb[1] = -(e3 + e2);
+  kr.tb[2] = R(-2) * e2 - kr.c[2];
+  const R c13 = R(13.0 / 3.0), eps4 = R(4) * WenoEps<R>::v;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    kl.be[i] = (c13 * kl.c[i]) * kl.c[i] + (kl.tb[i] * kl.tb[i] + eps4);
+    kr.be[i] = (c13 * kr.c[i]) * kr.c[i] + (kr.tb[i] * kr.tb[i] + eps4);
+  }
+  face_value_slope(kl, c[2], ql, dl);
   R m;
-  face_value_slope(vr, qr, m);
+  face_value_slope(kr, c[3], qr, m);
   dr = -m;
-  d0 = (c[1] - c[4] + R(15) * (c[3] - c[2])) * R(1.0 / 12.0);
+  d0 = (c[1] - c[4] + R(15) * e2) * R(1.0 / 12.0);
 }
 
 // ---------------------------------------------------------------------------
