@@ -42,7 +42,7 @@ UNIT = "cell-stage updates/s"
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
-    "sources_sha256": "ee74ee32dc7a0fe7f141d5ed2e88588921c03b27a133e7f01cb1b626673fc7e5",
+    "sources_sha256": "9392b1cc39c4ab1d203bba6d120fa003aa41d378fd483326acd8b70e3a942c2d",
     "fp64_flop_per_gp": 4023.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
     "fp32_flop_per_gp": 3743.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
 }
@@ -59,9 +59,9 @@ ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "ee74ee32dc7a0fe7f141d5ed2e88588921c03b27a133e7f01cb1b626673fc7e5",
-    "fetch_bytes": 9.5262e+09,
-    "write_bytes": 1.3527e+09,
+    "sources_sha256": "9392b1cc39c4ab1d203bba6d120fa003aa41d378fd483326acd8b70e3a942c2d",
+    "fetch_bytes": 9.4033e+09,
+    "write_bytes": 1.3422e+09,
 }
 
 # MI355X published peaks

@@ -20,8 +20,8 @@ def test_flux_flop_counts_match_profile():
         val = float(re.search(rf"\* {key}: ([0-9.]+)", text).group(1))
         assert bench.FLUX_EXECUTED[key] == val, key
     # the per-lane figure is what the table's FP64 rows give (mean of the directions, within 0.01%)
-    # (x and z faces in flux4_kernel<d>, y faces in flux_kernel<1, double>)
-    rows = re.findall(r"\| `hgks::flux(?:4_kernel<\d>|_kernel<\d, double>)` \|[^\n]*\| ([0-9.]+) \| [0-9.]+ \|", text)
+    # (x and z faces in flux4_kernel<d>, y faces in flux4y_kernel)
+    rows = re.findall(r"\| `hgks::flux(?:4_kernel<\d>|4y_kernel)` \|[^\n]*\| ([0-9.]+) \| [0-9.]+ \|", text)
     assert len(rows) == 3
     mean = sum(float(r) for r in rows) / 3
     assert abs(mean - bench.FLUX_EXECUTED["fp64_flop_per_gp"]) <= 1e-4 * mean
