@@ -524,7 +524,6 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
                                           R st2, const double rl[5], double* carry_area) {
   constexpr int D1 = (DIR + 1) % 3, D2 = (DIR + 2) % 3;
   const int tid = threadIdx.x;
-  GaussPoint<R> gp(gpi & 1);
   GasParams<R> g;
   g.gm1 = R(P.gm1);
   g.K = R(P.K);
@@ -621,10 +620,11 @@ __device__ __forceinline__ void flux_lane(Begin&& begin, Pair&& pair, Plain&& pl
   {
     R dq0n[5];
     begin(3);
+    const LinearWeights<R> lw(gpi & 1);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       plain(b_d0(k), pa[k]);
-      dq0n[k] = gauss_linear(pa[k], gp) * sn;
+      dq0n[k] = gauss_linear(pa[k], lw) * sn;
     }
     if constexpr (kCarry) {
       asm volatile("" ::: "memory");
@@ -699,7 +699,6 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
     const uint32_t inplane = (uint32_t)(b[1] - bo[1]) * (uint32_t)bp + (uint32_t)(b[0] - bo[0]);
     off[j] = (uint32_t)sizeof(R) * (uint32_t)b_pos<R>(inplane, g1, NB) + (second ? pair_off : 0u);
   }
-  GaussPoint<R> gp(g2);
   const R sn = R(gmem(P.dface[DIR])[f[DIR]]);
   const R st1 = R(gmem(P.dgp[D1])[2 * f[D1] + g1]);
   const R st2 = R(gmem(P.dgp[D2])[2 * f[D2] + g2]);
@@ -801,10 +800,11 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   R Fn[5], Fd[5];  // F^n and dF^n/dt at this lane's Gauss point
   {
     R dq0n[5];
+    const LinearWeights<R> lw(g2);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       stencil(b_d0(k), pa[k]);
-      dq0n[k] = gauss_linear(pa[k], gp) * sn;
+      dq0n[k] = gauss_linear(pa[k], lw) * sn;
     }
     flux_finish(dq0n, g, acc, Fn, Fd);
   }

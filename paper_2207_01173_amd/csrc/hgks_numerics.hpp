@@ -135,19 +135,6 @@ struct GaussConst {
   static constexpr double dd0 = 11.0 / 36.0 - 5.0 * r3 / 36.0, dd1 = 7.0 / 18.0, dd2 = 11.0 / 36.0 + 5.0 * r3 / 36.0;
 };
 
-// Position and linear weights of one Gauss point, chosen per lane at run time
-// (g = 0: s = -sqrt3/6, g = 1: s = +sqrt3/6; the weights mirror with s).
-template <class R> struct GaussPoint {
-  R s, dv0, dv1, dv2;
-  __device__ __forceinline__ explicit GaussPoint(int g) {
-    const bool p = g != 0;
-    s = p ? R(GaussConst::s) : R(-GaussConst::s);
-    dv0 = p ? R(GaussConst::dv0) : R(GaussConst::dv2);
-    dv1 = R(GaussConst::dv1);
-    dv2 = p ? R(GaussConst::dv2) : R(GaussConst::dv0);
-  }
-};
-
 // Both Gauss points of one stencil (index 0: s = -sqrt3/6, 1: s = +sqrt3/6)
 // from one set of candidates and WENO-Z factors.  At +s the value is
 // v2 + s sum w_k b_k with the value weights (dv0, dv1, dv2) and the slope
@@ -211,13 +198,34 @@ __device__ __forceinline__ void gauss_linear2(const R v[5], R val[2]) {
   val[1] = v[2] + s * (d0 * b0 + d1 * b1 + d2 * b2);
 }
 
-// Linear (fifth-order) value at a Gauss point: the quartic through the averages.
+// Linear (fifth-order) value at a Gauss point: the quartic through the
+// averages, v2 + s (dv0 b0 + dv1 b1 + dv2 b2) with the candidates' slopes b_k
+// written out, a fixed weighted sum of the five averages.  Weights at
+// s = +sqrt3/6; at -sqrt3/6 they apply to the reversed stencil.
+struct LinearGauss {
+  static constexpr double s = GaussConst::s, d0 = GaussConst::dv0, d1 = GaussConst::dv1, d2 = GaussConst::dv2;
+  static constexpr double w0 = s * d0 * 0.5;
+  static constexpr double w1 = s * (-2.0 * d0 - 0.5 * d1);
+  static constexpr double w2 = 1.0 + s * (1.5 * d0 - 1.5 * d2);
+  static constexpr double w3 = s * (0.5 * d1 + 2.0 * d2);
+  static constexpr double w4 = -s * d2 * 0.5;
+};
+// The weights of a lane's Gauss point (g = 1: +sqrt3/6, g = 0: -sqrt3/6).
+template <class R> struct LinearWeights {
+  R w[5];
+  __device__ __forceinline__ explicit LinearWeights(int g) {
+    using L = LinearGauss;
+    const bool p = g != 0;
+    w[0] = p ? R(L::w0) : R(L::w4);
+    w[1] = p ? R(L::w1) : R(L::w3);
+    w[2] = R(L::w2);
+    w[3] = p ? R(L::w3) : R(L::w1);
+    w[4] = p ? R(L::w4) : R(L::w0);
+  }
+};
 template <class R>
-__device__ __forceinline__ R gauss_linear(const R v[5], const GaussPoint<R>& gp) {
-  const R b0 = R(1.5) * v[2] - R(2) * v[1] + R(0.5) * v[0];
-  const R b1 = R(0.5) * (v[3] - v[1]);
-  const R b2 = R(2) * v[3] - R(1.5) * v[2] - R(0.5) * v[4];
-  return v[2] + gp.s * (gp.dv0 * b0 + gp.dv1 * b1 + gp.dv2 * b2);
+__device__ __forceinline__ R gauss_linear(const R v[5], const LinearWeights<R>& lw) {
+  return lw.w[0] * v[0] + lw.w[1] * v[1] + lw.w[2] * v[2] + lw.w[3] * v[3] + lw.w[4] * v[4];
 }
 
 // Value and slope at the right face (s = 1/2) of the centre cell: candidate
@@ -357,6 +365,28 @@ __device__ __forceinline__ R horner(R t, R p) {
 template <class R, class S, int N> __device__ __forceinline__ R series(R t) {
   return horner<R, S, N>(t, R(S::template coef<N>()));
 }
+// e^r = sum_n r^n / n!.
+struct ExpSeries {
+  template <int n> static constexpr double coef() { return 1.0 / Factorial<n>::value; }
+};
+
+// e^x for x <= 0.  FP64: x = k ln2 + r with k = rint(x / ln2) and
+// |r| <= ln2 / 2 (Cody-Waite reduction: ln 2 split into a head of 42
+// significant bits, so that k ln2_hi is exact for the |k| < 2^11 of the
+// exponent range, and the rounded remainder), e^r from its Taylor series of
+// degree 13 (first omitted term below 4e-18 of the sum), times 2^k.
+// Arguments below -1000 (and -inf) give 0.  FP32: the device library's exp.
+constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;   // ln 2 rounded to 42 bits
+constexpr double kLn2Lo = 0x1.ef35793c76730p-45;  // ln 2 - kLn2Hi, rounded
+__device__ __forceinline__ double exp_nonpos(double x) {
+  x = fmax(x, -1000.0);
+  const double k = __builtin_rint(x * 1.4426950408889634);  // x / ln 2
+  double r = fma(-k, kLn2Hi, x);
+  r = fma(-k, kLn2Lo, r);
+  return __builtin_amdgcn_ldexp(series<double, ExpSeries, 13>(r), (int)k);
+}
+__device__ __forceinline__ float exp_nonpos(float x) { return expf(x); }
+
 // Degrees for |x| <= 1/2 (t <= 1/4): the first omitted term is below 3e-18
 // (FP64) or 4e-10 (FP32) of the sum.
 template <class R> struct HalfSeries;
@@ -569,7 +599,7 @@ template <class R> struct GasParams {
 // Cn = (1, 0, 0, 0, 0, 0) and Cd = (0, 0, 1, 0, 0, 0) with no special case.
 template <class R>
 __device__ __forceinline__ void time_integrals(R tau, R itau, R dt, R Cn[6], R Cd[6]) {
-  const R h = tau > R(0) ? exp(-(R(0.5) * dt) * itau) : R(0);
+  const R h = tau > R(0) ? exp_nonpos(-(R(0.5) * dt) * itau) : R(0);
   const R o = R(1) - h, t2 = tau * tau, og = o * (R(3) - h), o2 = o * o;
   const R idt = pos_rcp(dt), i4dt2 = R(4) * idt * idt;
   Cn[0] = (dt - tau * og) * idt;
