@@ -42,9 +42,9 @@ UNIT = "cell-stage updates/s"
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
-    "sources_sha256": "9392b1cc39c4ab1d203bba6d120fa003aa41d378fd483326acd8b70e3a942c2d",
-    "fp64_flop_per_gp": 4023.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
-    "fp32_flop_per_gp": 3743.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
+    "sources_sha256": "b73b7fb72286e347228ef329ef7ee4fd77d4129e64c3f1036d225afe6f3dbd21",
+    "fp64_flop_per_gp": 3982.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
+    "fp32_flop_per_gp": 3698.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
 }
 # Bytes the method must move per cell-stage (FP64 state): stage 1 reads Q^n
 # and writes Q* and the S2O4 accumulator, stage 2 reads Q* and the
@@ -59,8 +59,8 @@ ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "9392b1cc39c4ab1d203bba6d120fa003aa41d378fd483326acd8b70e3a942c2d",
-    "fetch_bytes": 9.4033e+09,
+    "sources_sha256": "b73b7fb72286e347228ef329ef7ee4fd77d4129e64c3f1036d225afe6f3dbd21",
+    "fetch_bytes": 9.4041e+09,
     "write_bytes": 1.3422e+09,
 }
 
