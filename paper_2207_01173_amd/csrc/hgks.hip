@@ -666,7 +666,7 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   const int gpi = (tid >> 4) & 3;
   const int g1 = gpi >> 1, g2 = gpi & 1;
   const bool valid = f[0] < fe[0] && f[1] < fe[1] && f[2] < fe[2];
-  if (!valid) {  // keep the lane for the shuffles, on a valid face
+  if (!valid) {  // keep the lane for the exchanges, on a valid face
     f[0] = min(f[0], fe[0] - 1);
     f[1] = min(f[1], fe[1] - 1);
   }
@@ -856,7 +856,7 @@ __device__ __forceinline__ void flux_tile4(const double* __restrict__ B, const P
   const int gpi = (lane >> 4) & 3;
   const int g1 = gpi >> 1, g2 = gpi & 1;
   const bool valid = f[0] < fe[0] && f[D2] < fe[D2];
-  if (!valid) {  // keep the lane for the shuffles, on a real face
+  if (!valid) {  // keep the lane for the exchanges, on a real face
     f[0] = min(f[0], fe[0] - 1);
     f[D2] = min(f[D2], fe[D2] - 1);
   }
