@@ -127,9 +127,18 @@ __host__ __device__ inline void b_extents(const Params& P, int d, int be[3], int
   }
 }
 
+// t mod n for -n <= t < 2n: one correction either way, no integer division
+// (which takes some 40 vector instructions).
+__host__ __device__ __forceinline__ int wrap1(int t, int n) {
+  t = t < 0 ? t + n : t;
+  return t >= n ? t - n : t;
+}
+
 // One cell of the padded state, synthesised from the interior: periodic wrap,
 // or the isothermal-wall mirror (velocity reversed, same pressure,
 // temperature 2 T_w - T (not below 0.1 T_w), density p/T), all in FP64.
+// Every caller passes coordinates within three cells of the grid, and every
+// axis has at least 4 cells, so one wrap correction suffices.
 template <class S>
 __device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params& P, int c0, int c1, int c2,
                                           double v[5]) {
@@ -143,7 +152,7 @@ __device__ __forceinline__ void load_cell(const S* __restrict__ q, const Params&
         mirror = true;
         c[a] = c[a] < 0 ? -c[a] - 1 : 2 * N - 1 - c[a];
       } else {
-        c[a] = ((c[a] % N) + N) % N;
+        c[a] = wrap1(c[a], N);
       }
     }
   }
@@ -868,14 +877,16 @@ __device__ __forceinline__ void flux_tile4(const double* __restrict__ B, const P
   // entries tid + 256 k, so each wave's copy lands in 64 consecutive entries.
   // Row and face of those entries do not depend on k and the quantity is
   // 2 k + tid / 128, so one lane address serves every copy: the k-th is 2 k
-  // quantities (512 bytes) further.
+  // quantities (512 bytes) further.  The rows span -2 <= t <= 4 ceil(n/4) + 1,
+  // within one period either side for every n >= 4.
   __shared__ double2 stage[B_COUNT][FLUX4_ROWS][FLUX4_X];
   constexpr int kEntries = B_COUNT * FLUX4_ROWS * FLUX4_X;
   {
     const int r = (tid >> 4) & (FLUX4_ROWS - 1), fi = tid & (FLUX4_X - 1);
+    const int wu = __builtin_amdgcn_readfirstlane(w) & 3;  // LDS destinations in scalar registers
     int t = tc[D2] * FLUX4_P - 2 + r;
     if (P.bc[D2] == HGKS_BC_ISOTHERMAL_WALL) t = min(t, P.n[D2] + 1);
-    else t = ((t % P.n[D2]) + P.n[D2]) % P.n[D2];
+    else t = wrap1(t, P.n[D2]);
     int b[3];
     b[0] = min(tc[0] * FLUX4_X + fi, fe[0] - 1);
     b[D2] = t;
@@ -886,9 +897,9 @@ __device__ __forceinline__ void flux_tile4(const double* __restrict__ B, const P
             sizeof(double);
 #pragma unroll
     for (int k = 0; k < (kEntries + FLUX_THREADS - 1) / FLUX_THREADS; ++k)
-      if (FLUX_THREADS * k + 64 * w < kEntries)  // wave-uniform
+      if (FLUX_THREADS * k + 64 * wu < kEntries)  // wave-uniform
         dma16_to_lds(lane_src + (size_t)(2 * k) * 32 * sizeof(double),
-                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * w));
+                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * wu));
   }
   double sn = gmem(P.dface[DIR])[f[DIR]];
   double st1 = gmem(P.dgp[D1])[2 * f[D1] + g1];
@@ -974,8 +985,12 @@ __device__ __forceinline__ void flux_tile4y(const double* __restrict__ B, const 
   constexpr int kEntries = B_COUNT * FLUX4Y_Z * FLUX4Y_W;
   {
     const int r = (tid >> 5) & (FLUX4Y_Z - 1), ei = tid & (FLUX4Y_W - 1);
+    const int wu = __builtin_amdgcn_readfirstlane(w) & 3;  // LDS destinations in scalar registers
+    // -2 <= x <= 16 ceil(n_x / 16) + 1: within one period either side for
+    // n_x > 8; the few narrower grids take the division
     int x = tc[0] * FLUX4_X - 2 + min(ei, FLUX4_X + 3);
-    x = ((x % P.n[0]) + P.n[0]) % P.n[0];
+    if (P.n[0] > 8) x = wrap1(x, P.n[0]);
+    else x = ((x % P.n[0]) + P.n[0]) % P.n[0];
     int b[3];
     b[0] = x;
     b[1] = f[1];
@@ -986,9 +1001,9 @@ __device__ __forceinline__ void flux_tile4y(const double* __restrict__ B, const 
             sizeof(double);
 #pragma unroll
     for (int k = 0; k < (kEntries + FLUX_THREADS - 1) / FLUX_THREADS; ++k)
-      if (FLUX_THREADS * k + 64 * w < kEntries)  // wave-uniform
+      if (FLUX_THREADS * k + 64 * wu < kEntries)  // wave-uniform
         dma16_to_lds(lane_src + (size_t)(2 * k) * 32 * sizeof(double),
-                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * w));
+                     reinterpret_cast<double*>(&stage[0][0][0]) + 2 * (FLUX_THREADS * k + 64 * wu));
   }
   double sn = gmem(P.dface[DIR])[f[DIR]];
   double st1 = gmem(P.dgp[D1])[2 * f[D1] + g1];

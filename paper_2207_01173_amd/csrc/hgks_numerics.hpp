@@ -728,8 +728,11 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
   State<R> s = primitive(q, g.gm1, ir, ihl);
   VW<R> e;
   vw_moments(s, ihl, g.K, e);
-  // micro-slopes of the three directions: <(a_d . psi) psi> = dq_d / rho
-  const SlopeSolve<R> Sq = slope_solver(s, ihl, g.K3, g.iK3, ir);
+  // micro-slopes of the three directions times the side's density,
+  // <(a_d . psi) psi> = dq_d: every term below that is linear in them (the
+  // C5 and C6 moments, the time slope, the tangential slopes of Q0) then
+  // carries its factor rho already
+  const SlopeSolve<R> Sq = slope_solver(s, ihl, g.K3, g.iK3, R(1));
   R a[3][5];
 #pragma unroll
   for (int d = 0; d < 3; ++d) slope_solve(Sq, dq[d], a[d]);
@@ -748,15 +751,11 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
   else chain<R, 7>(s.U, ihl, Acc.rm0, Acc.rm1, Mh);
   const Quad<R> unit[1] = {quad_c(R(1), e)};
   const Quad<R> qA = quad_p(A, e);
-  const R rho = s.rho;
   const R U0 = Acc.s0.U, V0 = Acc.s0.V, W0 = Acc.s0.W;
-  // the side's density times the time coefficients of its three terms
-  R rn[3], rd[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    rn[i] = rho * Acc.Cn[3 + i];
-    rd[i] = rho * Acc.Cd[3 + i];
-  }
+  // the time coefficients of the side's three terms, times its density for
+  // the first (the other two carry it through the slopes)
+  const R rn[3] = {s.rho * Acc.Cn[3], Acc.Cn[4], Acc.Cn[5]};
+  const R rd[3] = {s.rho * Acc.Cd[3], Acc.Cd[4], Acc.Cd[5]};
   {
     R X1[5], X2[5], X3[5];
     assemble<R, 1, 1>(unit, Mh, X1);
@@ -783,7 +782,7 @@ __device__ __forceinline__ void flux_side(const R q[5], const R dq[3][5], const 
     R t[5];
     assemble_apsi<R, 0>(a[d], quad_p(a[d], e), e, Mh, t);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Acc.dq0t[d - 1][k] += rho * t[k];
+    for (int k = 0; k < 5; ++k) Acc.dq0t[d - 1][k] += t[k];
   }
 }
 
@@ -799,28 +798,23 @@ __device__ __forceinline__ void flux_finish(const R dq0n[5], const GasParams<R>&
   vw_moments(s0, ihl0, g.K, e);
   R Mf[7];
   chain<R, 7>(s0.U, ihl0, R(1), s0.U, Mf);
-  R a[3][5];
+  R a[3][5];  // the equilibrium's micro-slopes times rho0, as on the sides
   {
-    const SlopeSolve<R> Sq = slope_solver(s0, ihl0, g.K3, g.iK3, pos_rcp(s0.rho));
+    const SlopeSolve<R> Sq = slope_solver(s0, ihl0, g.K3, g.iK3, R(1));
     slope_solve(Sq, dq0n, a[0]);
     slope_solve(Sq, Acc.dq0t[0], a[1]);
     slope_solve(Sq, Acc.dq0t[1], a[2]);
   }
   Quad<R> pi[4];
   series_pi(a, e, pi);
-  R T[5];  // sum_d <s_d (a_d . psi) psi>_0
+  R T[5];  // rho0 sum_d <s_d (a_d . psi) psi>_0
   assemble<R, 0, 4>(pi, Mf, T);
   R A[5];
   slope_solve(slope_solver(s0, ihl0, g.K3, g.iK3, R(-1)), T, A);
   const Quad<R> unit[1] = {quad_c(R(1), e)};
   const Quad<R> qA = quad_p(A, e);
-  const R rho = s0.rho;
-  R rn[3], rd[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    rn[i] = rho * Acc.Cn[i];
-    rd[i] = rho * Acc.Cd[i];
-  }
+  const R rn[3] = {s0.rho * Acc.Cn[0], Acc.Cn[1], Acc.Cn[2]};
+  const R rd[3] = {s0.rho * Acc.Cd[0], Acc.Cd[1], Acc.Cd[2]};
   R X1[5], X2[5], X3[5];
   assemble<R, 1, 1>(unit, Mf, X1);
   assemble<R, 1, 4>(pi, Mf, X2);
