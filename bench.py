@@ -42,9 +42,9 @@ UNIT = "cell-stage updates/s"
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
-    "sources_sha256": "082e45d8818b839c47fd89300e9b9d0718c94465a3eb843c8a26f38c15d774db",
-    "fp64_flop_per_gp": 3982.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
-    "fp32_flop_per_gp": 3698.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
+    "sources_sha256": "cb1cf779222471a25f67b92758d8c0458b5b03035a892e3be00e7f7fd37187d9",
+    "fp64_flop_per_gp": 3936.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
+    "fp32_flop_per_gp": 3652.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
 }
 # Bytes the method must move per cell-stage (FP64 state): stage 1 reads Q^n
 # and writes Q* and the S2O4 accumulator, stage 2 reads Q* and the
@@ -59,8 +59,8 @@ ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "082e45d8818b839c47fd89300e9b9d0718c94465a3eb843c8a26f38c15d774db",
-    "fetch_bytes": 9.4041e+09,
+    "sources_sha256": "cb1cf779222471a25f67b92758d8c0458b5b03035a892e3be00e7f7fd37187d9",
+    "fetch_bytes": 9.4035e+09,
     "write_bytes": 1.3422e+09,
 }
 
