@@ -665,7 +665,19 @@ __device__ __forceinline__ void flux_tile(const R* __restrict__ B, const Params&
   b_extents(P, DIR, be, bo);
   int nt[3], tc[3];
   flux_tile_counts<TX>(P, DIR, nt);
-  tile_coords(lin, nt, D2, tc);  // t2 tiles adjacent
+  if (D2 != 0 && (nt[0] & 1) == 0) {
+    // x-tile pairs, then t2: the two tiles of a pair read the two halves of
+    // each 128-byte line of FP32 face data one after the other, and t2
+    // neighbours (sharing four of five stencil rows) are two blocks apart
+    const int xh = lin & 1;
+    int r = lin >> 1;
+    tc[D2] = r % nt[D2];
+    r /= nt[D2];
+    tc[0] = 2 * (r % (nt[0] >> 1)) + xh;
+    tc[3 - D2] = r / (nt[0] >> 1);
+  } else {
+    tile_coords(lin, nt, D2, tc);  // t2 tiles adjacent
+  }
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   int f[3];
