@@ -517,10 +517,11 @@ __device__ __forceinline__ void series_pi(const R a[3][5], const VW<R>& e, Quad<
 }
 
 // Closed-form solution of <(a . psi) psi> = c b for a Maxwellian state
-// (normalised by density).  The common scale c of the right-hand side (1/rho
-// for slopes of conserved variables, -1 for the time-derivative condition)
-// is folded into the solve's constants: t1 = 2 lambda c and
-// t2 = (2 lambda)^2 c / (K + 3).
+// (normalised by density).  The common scale c of the right-hand side is
+// folded into the solve's constants, t1 = 2 lambda c and
+// t2 = (2 lambda)^2 c / (K + 3): the flux solves with c = 1 for the
+// micro-slopes times the density (b the slopes of the conserved variables)
+// and with c = -1 for the time-derivative condition.
 template <class R> struct SlopeSolve { R U, V, W, q2, c, t1, t2; };
 
 template <class R>
