@@ -33,11 +33,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("ma", [0.1, 0.29])
+@pytest.mark.parametrize("ma", [0.1, 0.29, 0.5, 1.0])
 def test_mixed_precision_error_is_small_and_stated(hg, oracle, ma):
     """Mixed path vs the FP64 oracle after 10 steps of the 32^3 TGV: the
     state error (relative max-norm per component) is reported and bounded;
-    the FP64 path on the same case sits at rounding level."""
+    the FP64 path on the same case sits at rounding level.  Ma 0.5 and 1.0
+    (the compressible sweep of Sec. 4.1) take the FP32 half-space moments
+    off their Taylor series (|sqrt(lambda) U| > 1/2 on part of the grid)."""
     p = W.tgv_params(32, ma=ma, re=1600.0, pr=0.72, cfl=0.5)
     q0 = W.tgv_initial(p)
     dt = oracle.cfl_dt(p, q0)
@@ -181,7 +183,7 @@ def test_batch_rejects_mass_flux_flag(hg):
     assert e.value.status == hg.HGKS_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("ma", [0.1, 0.29])
+@pytest.mark.parametrize("ma", [0.1, 0.29, 0.5, 1.0])
 def test_fp32_error_is_small_and_stated(hg, oracle, ma):
     """Whole-code FP32 path (state, stages and update in FP32) vs the FP64
     oracle after 10 steps of the 32^3 TGV.  The state is rounded to FP32 twice
