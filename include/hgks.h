@@ -53,8 +53,8 @@ extern "C" {
  * target is the volume mean of rho U of the state given to hgks_init; after
  * each step the x body force becomes f - (2 e^{n+1} - e^n) / (rho_b dt), e the
  * deviation of the step's mean rho U from the target, rho_b the initial mean
- * density; body_force[0] is the starting force.  Single-instance contexts
- * only (hgks_batch_* return HGKS_E_UNSUPPORTED). */
+ * density; body_force[0] is the starting force.  Per instance, in a
+ * single-instance context or as a batch member alike. */
 #define HGKS_FLAG_CONSTANT_MASS_FLUX 1
 
 typedef struct hgks_ctx_s* hgks_ctx;
@@ -211,11 +211,13 @@ hgks_status hgks_fma_probe(double* out_dev, int32_t blocks, int32_t iters, void*
  * state), each S2O4 step is captured once in a HIP graph and replayed, and
  * each instance takes its own CFL time step.  Instance i's state q_devs[i] has
  * the single-instance layout, and each instance's arithmetic is that of a
- * single-instance run.  For the callers running many small problems in one
+ * single-instance run (the constant-mass-flux controller included, for the
+ * members that set it).  For the callers running many small problems in one
  * stream (ensembles, parameter sweeps).  ws_dev must be 256-byte aligned and
  * hip_stream a created stream (graph capture).  Errors: HGKS_E_INVALID for any
- * invalid member config (its index is reported by hgks_last_error), or work
- * lists beyond 2^30 tiles; HGKS_E_DEVICE. */
+ * invalid member config (its index is reported by hgks_last_error), members
+ * of different precisions, or work lists beyond 2^30 tiles;
+ * HGKS_E_UNSUPPORTED for whole-code FP32 members; HGKS_E_DEVICE. */
 hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes);
 hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev,
                             size_t ws_bytes, void* hip_stream, hgks_ctx* out);

@@ -1397,6 +1397,9 @@ struct BatchEntry {
   Scalars* sc;
   double* qref;
   double cfl;
+  double* mpart;      // per-block sums of rho U dV (constant-mass-flux members)
+  const double* mf;   // the controller's {rho_b, m_t}
+  double inv_vol;     // 1 / domain volume
 };
 enum { PRE_RECON = 0, PRE_FLUX = 3, PRE_CELL = 9, PRE_ROWS = 10 };  // flux rows: TX 16, 32 x 3 directions
 template <int TX> constexpr int flux_row(int d) { return PRE_FLUX + 3 * (TX == 16 ? 0 : 1) + d; }
@@ -1454,7 +1457,7 @@ __global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T
   if (t >= t1) return;
   int local;
   const BatchEntry& e = T.E[find_instance(T, PRE_CELL, t, local)];
-  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, nullptr, (size_t)local);
+  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, e.mpart, (size_t)local);
 }
 
 // Start of a batched step: each instance takes its own CFL time step.
@@ -1501,8 +1504,10 @@ __global__ void mass_flux_init_kernel(const double* __restrict__ fin, double inv
   sc->m_prev = mf[1];
 }
 
-__global__ __launch_bounds__(256) void mass_flux_kernel(const double* __restrict__ mpart, int nb, double inv_vol,
-                                                        const double* __restrict__ mf, Scalars* __restrict__ sc) {
+// One block of 256 threads: the volume mean of rho U from the stage-2 block
+// sums (fixed order, so deterministic) and the force update.
+__device__ __forceinline__ void mass_flux_update(const double* __restrict__ mpart, int nb, double inv_vol,
+                                                 const double* __restrict__ mf, Scalars* __restrict__ sc) {
   __shared__ double red[256];
   double t = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) t += mpart[b];
@@ -1518,6 +1523,18 @@ __global__ __launch_bounds__(256) void mass_flux_kernel(const double* __restrict
     sc->force_x -= (2.0 * e1 - e0) / (mf[0] * sc->dt);
     sc->m_prev = m;
   }
+}
+__global__ __launch_bounds__(256) void mass_flux_kernel(const double* __restrict__ mpart, int nb, double inv_vol,
+                                                        const double* __restrict__ mf, Scalars* __restrict__ sc) {
+  mass_flux_update(mpart, nb, inv_vol, mf, sc);
+}
+// The controller of every constant-mass-flux member of a batch: block i
+// serves member i, the same reduction as a single instance's (the other
+// members' blocks return at once).
+__global__ __launch_bounds__(256) void mass_flux_batch_kernel(BatchTable T) {
+  const BatchEntry& e = T.E[blockIdx.x];
+  if (!(e.P.flags & HGKS_FLAG_CONSTANT_MASS_FLUX)) return;
+  mass_flux_update(e.mpart, (int)((cells(e.P) + CELL_THREADS - 1) / CELL_THREADS), e.inv_vol, e.mf, e.sc);
 }
 
 // ---- device-side set-up (the entry point that takes no host buffers) ------
@@ -1719,6 +1736,7 @@ struct hgks_ctx_s {
   std::vector<int> pre;          // host copy of the prefix rows
   std::vector<int> group_first;  // member groups [group_first[g], group_first[g + 1])
   int tx = 16, group_mib = 0, tune_source = 0;
+  bool mass_flux_members = false;  // a member runs the constant-mass-flux controller
   hipGraph_t graph = nullptr;      // batched step, or the single-instance step (hgks_step)
   hipGraphExec_t exec = nullptr;
   double dt_fixed = 0.0;           // last time-step rule written to the device scalars
@@ -2036,6 +2054,8 @@ static void enqueue_batch_step(hgks_ctx b) {
   hipLaunchKernelGGL(update_batch_kernel<1>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
   enqueue_batch_fluxes(b, 1);
   hipLaunchKernelGGL(update_batch_kernel<2>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
+  if (b->mass_flux_members)
+    hipLaunchKernelGGL(mass_flux_batch_kernel, dim3(T.n), dim3(256), 0, b->stream, T);
 }
 
 // Milliseconds of `reps` runs of fn on the stream, timed with events.
@@ -2215,6 +2235,12 @@ static hgks_status batch_init_body(hgks_ctx b, int n, const hgks_config* cfgs, d
     e.sc = m->sc;
     e.qref = m->qref;
     e.cfl = cfgs[i].cfl;
+    e.mpart = m->mpart;
+    e.mf = m->mf;
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= cfgs[i].hi[a] - cfgs[i].lo[a];
+    e.inv_vol = 1.0 / vol;
+    if (cfgs[i].flags & HGKS_FLAG_CONSTANT_MASS_FLUX) b->mass_flux_members = true;
   }
   b->pre = batch_prefix(n, cfgs);
   const std::vector<int> coarse = batch_coarse(n, b->pre, b->table.coarse_off);
@@ -2545,7 +2571,7 @@ hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t
   for (int i = 0; i < n; ++i) {
     if (validate(&cfgs[i], nullptr) != HGKS_OK) return HGKS_E_INVALID;
     if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
-    if (cfgs[i].flags != 0 || cfgs[i].precision == HGKS_FP32) return HGKS_E_UNSUPPORTED;
+    if (cfgs[i].precision == HGKS_FP32) return HGKS_E_UNSUPPORTED;
     total += align256(make_layout(cfgs[i]).total);
   }
   const std::vector<int> pre = batch_prefix(n, cfgs);

@@ -170,15 +170,19 @@ def hgks_step(ctx, nsteps: int, dt_fixed: float = 0.0):
     _check(lib().hgks_step(ctx, int(nsteps), float(dt_fixed)), ctx)
 
 
-def hgks_stats(ctx) -> dict:
-    s = hgks_stats_t()
-    _check(lib().hgks_stats(ctx, ctypes.byref(s)), ctx)
+def _stats_dict(s: hgks_stats_t) -> dict:
     return {
         "t": s.t, "dt_last": s.dt_last, "steps": s.steps, "Ek": s.Ek, "eps_sol": s.eps_sol,
         "eps_dil": s.eps_dil, "eps_com": s.eps_com, "total": np.array(s.total[:]),
         "max_abs": np.array(s.max_abs[:]), "min_p": s.min_p, "min_rho": s.min_rho, "nonfinite": s.nonfinite,
         "body_force_x": s.body_force_x,
     }
+
+
+def hgks_stats(ctx) -> dict:
+    s = hgks_stats_t()
+    _check(lib().hgks_stats(ctx, ctypes.byref(s)), ctx)
+    return _stats_dict(s)
 
 
 def hgks_dt(ctx) -> float:
@@ -248,11 +252,7 @@ def hgks_batch_step(ctx, nsteps: int):
 def hgks_batch_stats(ctx, i: int) -> dict:
     s = hgks_stats_t()
     _check(lib().hgks_batch_stats(ctx, int(i), ctypes.byref(s)), ctx)
-    return {
-        "t": s.t, "dt_last": s.dt_last, "steps": s.steps, "Ek": s.Ek, "eps_sol": s.eps_sol,
-        "eps_dil": s.eps_dil, "eps_com": s.eps_com, "total": np.array(s.total[:]),
-        "max_abs": np.array(s.max_abs[:]), "min_p": s.min_p, "min_rho": s.min_rho, "nonfinite": s.nonfinite,
-    }
+    return _stats_dict(s)
 
 
 BATCH_INFO_KEYS = ("instances", "flux_tile_x", "group_mib", "groups", "flux_tiles", "tune_source",

@@ -174,13 +174,49 @@ def test_channel_mass_flux_parity(hg, oracle):
     assert abs(st["body_force_x"] - f_ref) <= tol_f
 
 
-def test_batch_rejects_mass_flux_flag(hg):
-    p, _ = channel_case((8, 16, 8))
-    p["mass_flux_control"] = True
-    cfg = hg.make_config(p)
-    with pytest.raises(hg.HGKSError) as e:
-        hg.hgks_batch_workspace_size([cfg])
-    assert e.value.status == hg.HGKS_E_UNSUPPORTED
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_mass_flux_members(hg, oracle, tmp_path, precision):
+    """Batched members with the constant-mass-flux controller (two walled,
+    stretched channels, one started from another force) beside a periodic
+    TGV member without it: after 5 CFL steps every member equals its
+    standalone run bit for bit, state, time step and force (each member's
+    controller runs the single-instance reduction), and the FP64 channel
+    member matches the oracle to 1e-11 as the single-instance run does."""
+    import os
+
+    os.environ["HGKS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        prec = hg.FP64 if precision == "fp64" else hg.MIXED
+        pa, qa = channel_case((16, 24, 12))
+        pa["mass_flux_control"] = True
+        pb, qb = channel_case((8, 16, 8))
+        pb["mass_flux_control"] = True
+        pb["body_force"] = (2e-3, 0.0, 0.0)
+        pt = W.tgv_params((12, 12, 12), ma=0.3, re=800.0)
+        qt = W.tgv_initial(pt)
+        ens = [(pa, qa), (pt, qt), (pb, qb)]
+        b = hg.Batch([p for p, _ in ens], [q for _, q in ens], precision=prec)
+        say(f"batch with mass-flux members ({precision}):", b.info())
+        b.step(5)
+        for i, (p, q) in enumerate(ens):
+            s = hg.Solver(p, q, precision=prec)
+            s.step(5, 0.0)
+            ref = s.state()
+            st = s.stats()
+            s.close()
+            bs = b.stats(i)
+            say(f"  member {i} {p['n']}: force {bs['body_force_x']!r} standalone {st['body_force_x']!r}")
+            np.testing.assert_array_equal(b.state(i), ref)
+            assert bs["body_force_x"] == st["body_force_x"] and bs["dt_last"] == st["dt_last"]
+            assert bs["steps"] == 5
+        if prec == hg.FP64:
+            ref, _, _ = oracle.step_force(pa, qa, 5, 0.0)
+            err = rel_err(b.state(0), ref)
+            say("  channel member vs oracle", err)
+            assert (err <= 1e-11).all()
+        b.close()
+    finally:
+        del os.environ["HGKS_TUNE_CACHE"]
 
 
 @pytest.mark.parametrize("ma", [0.1, 0.29, 0.5, 1.0])
