@@ -216,8 +216,10 @@ hgks_status hgks_fma_probe(double* out_dev, int32_t blocks, int32_t iters, void*
  * stream (ensembles, parameter sweeps).  ws_dev must be 256-byte aligned and
  * hip_stream a created stream (graph capture).  Errors: HGKS_E_INVALID for any
  * invalid member config (its index is reported by hgks_last_error), members
- * of different precisions, or work lists beyond 2^30 tiles;
- * HGKS_E_UNSUPPORTED for whole-code FP32 members; HGKS_E_DEVICE. */
+ * of different precisions, or work lists beyond 2^30 tiles; HGKS_E_DEVICE.
+ * Whole-code FP32 members step on FP32 working copies of their states, which
+ * hgks_batch_step fills from the callers' states before its steps and writes
+ * back after them, as hgks_step does. */
 hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t* bytes);
 hgks_status hgks_batch_init(int32_t n, const hgks_config* cfgs, double* const* q_devs, void* ws_dev,
                             size_t ws_bytes, void* hip_stream, hgks_ctx* out);

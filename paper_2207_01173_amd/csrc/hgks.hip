@@ -1397,6 +1397,7 @@ struct BatchEntry {
   Scalars* sc;
   double* qref;
   double cfl;
+  float* q32;         // whole-code FP32 members: the FP32 working copy of the state
   double* mpart;      // per-block sums of rho U dV (constant-mass-flux members)
   const double* mf;   // the controller's {rho_b, m_t}
   double inv_vol;     // 1 / domain volume
@@ -1427,14 +1428,17 @@ __device__ __forceinline__ int find_instance(const BatchTable& T, int row, int t
 // The batched kernels run one block per work item of the slice [t0, t1) of
 // the concatenated work list (all members, or a group of consecutive members);
 // blocks are XCD-remapped so each XCD's L2 holds neighbouring tiles.
-template <int DIR, class R>
+template <int DIR, class R, class ST>
 __global__ __launch_bounds__(RECON_THREADS) void recon_batch_kernel(BatchTable T, int t0, int t1, int src_qs) {
   __shared__ R A[25][recon_lds_faces<DIR, R>()];
   const int t = t0 + xcd_linear_block(gridDim.x);
   if (t >= t1) return;
   int local;
   const BatchEntry& e = T.E[find_instance(T, PRE_RECON + DIR, t, local)];
-  recon_tile<DIR, R>(src_qs ? e.qs : e.q, e.P, e.qref, static_cast<R*>(e.B), local, A);
+  const ST* src;
+  if constexpr (sizeof(ST) == 4) src = src_qs ? reinterpret_cast<const float*>(e.qs) : e.q32;
+  else src = src_qs ? e.qs : e.q;
+  recon_tile<DIR, R, ST>(src, e.P, e.qref, static_cast<R*>(e.B), local, A);
 }
 
 template <int DIR, class R, int TX>
@@ -1451,13 +1455,17 @@ __global__ __launch_bounds__(FLUX_THREADS, FLUX_MIN_BLOCKS) void flux_batch_kern
     flux_tile<DIR, R, TX>(static_cast<const R*>(e.B), e.P, e.qref, gmem(e.sc)->dt, e.F[DIR], local);
 }
 
-template <int STAGE>
+template <int STAGE, class S>
 __global__ __launch_bounds__(CELL_THREADS) void update_batch_kernel(BatchTable T, int t0, int t1) {
   const int t = t0 + xcd_linear_block(gridDim.x);
   if (t >= t1) return;
   int local;
   const BatchEntry& e = T.E[find_instance(T, PRE_CELL, t, local)];
-  update_block<STAGE>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, e.mpart, (size_t)local);
+  if constexpr (sizeof(S) == 4)
+    update_block<STAGE, float>(e.q32, reinterpret_cast<float*>(e.qs), reinterpret_cast<float*>(e.acc), e.F[0],
+                               e.F[1], e.F[2], e.P, e.sc, e.mpart, (size_t)local);
+  else
+    update_block<STAGE, double>(e.q, e.qs, e.acc, e.F[0], e.F[1], e.F[2], e.P, e.sc, e.mpart, (size_t)local);
 }
 
 // Start of a batched step: each instance takes its own CFL time step.
@@ -2018,31 +2026,47 @@ static void batch_set_groups(hgks_ctx b, int mib) {
   b->group_first.push_back(n);
 }
 
-template <int DIR, class R, int TX>
+template <int DIR, class R, int TX, class ST>
 static void enqueue_batch_direction(hgks_ctx b, int src_qs) {
   const BatchTable T = b->table;
   for (size_t g = 0; g + 1 < b->group_first.size(); ++g) {
     const int m0 = b->group_first[g], m1 = b->group_first[g + 1];
     const int r0 = batch_item(b, PRE_RECON + DIR, m0), r1 = batch_item(b, PRE_RECON + DIR, m1);
-    hipLaunchKernelGGL((recon_batch_kernel<DIR, R>), dim3(r1 - r0), dim3(RECON_THREADS), 0, b->stream, T, r0, r1,
-                       src_qs);
+    hipLaunchKernelGGL((recon_batch_kernel<DIR, R, ST>), dim3(r1 - r0), dim3(RECON_THREADS), 0, b->stream, T, r0,
+                       r1, src_qs);
     const int f0 = batch_item(b, flux_row<TX>(DIR), m0), f1 = batch_item(b, flux_row<TX>(DIR), m1);
     hipLaunchKernelGGL((flux_batch_kernel<DIR, R, TX>), dim3(f1 - f0), dim3(FLUX_THREADS), 0, b->stream, T, f0, f1);
   }
 }
-template <class R, int TX>
+template <class R, int TX, class ST>
 static void enqueue_batch_fluxes_tx(hgks_ctx b, int src_qs) {
-  enqueue_batch_direction<0, R, TX>(b, src_qs);
-  enqueue_batch_direction<1, R, TX>(b, src_qs);
-  enqueue_batch_direction<2, R, TX>(b, src_qs);
+  enqueue_batch_direction<0, R, TX, ST>(b, src_qs);
+  enqueue_batch_direction<1, R, TX, ST>(b, src_qs);
+  enqueue_batch_direction<2, R, TX, ST>(b, src_qs);
 }
 static void enqueue_batch_fluxes(hgks_ctx b, int src_qs) {
-  if (precision_mixed(b->cfg)) {
-    if (b->tx == 32) enqueue_batch_fluxes_tx<float, 32>(b, src_qs);
-    else enqueue_batch_fluxes_tx<float, 16>(b, src_qs);
+  if (precision_fp32(b->cfg)) {
+    if (b->tx == 32) enqueue_batch_fluxes_tx<float, 32, float>(b, src_qs);
+    else enqueue_batch_fluxes_tx<float, 16, float>(b, src_qs);
+  } else if (precision_mixed(b->cfg)) {
+    if (b->tx == 32) enqueue_batch_fluxes_tx<float, 32, double>(b, src_qs);
+    else enqueue_batch_fluxes_tx<float, 16, double>(b, src_qs);
   } else {
-    if (b->tx == 32) enqueue_batch_fluxes_tx<double, 32>(b, src_qs);
-    else enqueue_batch_fluxes_tx<double, 16>(b, src_qs);
+    if (b->tx == 32) enqueue_batch_fluxes_tx<double, 32, double>(b, src_qs);
+    else enqueue_batch_fluxes_tx<double, 16, double>(b, src_qs);
+  }
+}
+// Whole-code FP32 members: the callers' FP64 states into the FP32 working
+// copies (to_fp32) or back, as a single-instance hgks_step does around its
+// steps.
+static void batch_convert_states(hgks_ctx b, bool to_fp32) {
+  for (hgks_ctx m : b->members) {
+    const size_t n = 5 * cells(m->P);
+    const unsigned g = (unsigned)((n + CELL_THREADS - 1) / CELL_THREADS);
+    if (to_fp32)
+      hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(CELL_THREADS), 0, b->stream, m->q, m->q32, n);
+    else
+      hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(CELL_THREADS), 0, b->stream, m->q32, m->q, n);
   }
 }
 // One full batched S2O4 step on the stream (also what the graph captures).
@@ -2051,9 +2075,15 @@ static void enqueue_batch_step(hgks_ctx b) {
   const int nc = batch_item(b, PRE_CELL, T.n);
   hipLaunchKernelGGL(begin_step_batch_kernel, dim3((T.n + 63) / 64), dim3(64), 0, b->stream, T);
   enqueue_batch_fluxes(b, 0);
-  hipLaunchKernelGGL(update_batch_kernel<1>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
+  if (precision_fp32(b->cfg))
+    hipLaunchKernelGGL((update_batch_kernel<1, float>), dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
+  else
+    hipLaunchKernelGGL((update_batch_kernel<1, double>), dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
   enqueue_batch_fluxes(b, 1);
-  hipLaunchKernelGGL(update_batch_kernel<2>, dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
+  if (precision_fp32(b->cfg))
+    hipLaunchKernelGGL((update_batch_kernel<2, float>), dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
+  else
+    hipLaunchKernelGGL((update_batch_kernel<2, double>), dim3(nc), dim3(CELL_THREADS), 0, b->stream, T, 0, nc);
   if (b->mass_flux_members)
     hipLaunchKernelGGL(mass_flux_batch_kernel, dim3(T.n), dim3(256), 0, b->stream, T);
 }
@@ -2235,6 +2265,7 @@ static hgks_status batch_init_body(hgks_ctx b, int n, const hgks_config* cfgs, d
     e.sc = m->sc;
     e.qref = m->qref;
     e.cfl = cfgs[i].cfl;
+    e.q32 = m->q32;
     e.mpart = m->mpart;
     e.mf = m->mf;
     double vol = 1.0;
@@ -2257,6 +2288,8 @@ static hgks_status batch_init_body(hgks_ctx b, int n, const hgks_config* cfgs, d
   b->table.pre = dpre;
   b->table.coarse = dcoarse;
   b->table.n = n;
+  // the autotuner's reconstructions read the FP32 members' working copies
+  if (precision_fp32(b->cfg)) batch_convert_states(b, true);
   const hgks_status st = batch_autotune(b);
   if (st != HGKS_OK) return st;
   // capture one step
@@ -2571,7 +2604,6 @@ hgks_status hgks_batch_workspace_size(int32_t n, const hgks_config* cfgs, size_t
   for (int i = 0; i < n; ++i) {
     if (validate(&cfgs[i], nullptr) != HGKS_OK) return HGKS_E_INVALID;
     if (cfgs[i].precision != cfgs[0].precision) return HGKS_E_INVALID;
-    if (cfgs[i].precision == HGKS_FP32) return HGKS_E_UNSUPPORTED;
     total += align256(make_layout(cfgs[i]).total);
   }
   const std::vector<int> pre = batch_prefix(n, cfgs);
@@ -2613,7 +2645,12 @@ hgks_status hgks_batch_step(hgks_ctx ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0 || ctx->members.empty() || !ctx->exec) return HGKS_E_INVALID;
   for (hgks_ctx m : ctx->members)
     if (m->latched != HGKS_OK) return m->latched;
+  if (nsteps == 0) return HGKS_OK;
+  const bool fp32 = precision_fp32(ctx->cfg);
+  if (fp32) batch_convert_states(ctx, true);
   for (int s = 0; s < nsteps; ++s) HIP_TRY(ctx, hipGraphLaunch(ctx->exec, ctx->stream));
+  if (fp32) batch_convert_states(ctx, false);
+  HIP_TRY(ctx, hipGetLastError());
   return HGKS_OK;
 }
 

@@ -109,8 +109,8 @@ def test_largest_grids():
 
 
 def test_batch_rejects_unsupported_members():
-    """Batched members must share one precision, FP64 or mixed (whole-code
-    FP32 members are unsupported); the constant-mass-flux flag is per member."""
+    """Batched members must share one precision (FP64, mixed or whole-code
+    FP32); the constant-mass-flux flag is per member."""
     ens = [W.tgv_params(12), W.tgv_params((16, 12, 8))]
     cfgs = [hgks.make_config(p) for p in ens]
     assert hgks.hgks_batch_workspace_size(cfgs) > 0
@@ -121,6 +121,8 @@ def test_batch_rejects_unsupported_members():
     flagged = [hgks.make_config(dict(ens[0], mass_flux_control=True)), cfgs[1]]
     assert hgks.hgks_batch_workspace_size(flagged) == hgks.hgks_batch_workspace_size(cfgs)
     fp32 = [hgks.make_config(p, hgks.FP32) for p in ens]
+    assert hgks.hgks_batch_workspace_size(fp32) > hgks.hgks_batch_workspace_size(cfgs) // 2
+    mixed32 = [hgks.make_config(ens[0], hgks.FP32), hgks.make_config(ens[1], hgks.MIXED)]
     with pytest.raises(hgks.HGKSError) as e:
-        hgks.hgks_batch_workspace_size(fp32)
-    assert e.value.status == hgks.HGKS_E_UNSUPPORTED
+        hgks.hgks_batch_workspace_size(mixed32)
+    assert e.value.status == hgks.HGKS_E_INVALID

@@ -38,12 +38,14 @@ def small_ensemble():
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_batch_members_equal_standalone_runs(hg, tmp_path, precision):
     """Each member of a batched run equals its standalone run bit for bit:
-    the same tile functions, per-face arithmetic and per-instance CFL step."""
+    the same tile functions, per-face arithmetic and per-instance CFL step
+    (whole-code FP32: the same rounding of the state into the FP32 working
+    copy and back around each call)."""
     os.environ["HGKS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
-    prec = hg.FP64 if precision == "fp64" else hg.MIXED
+    prec = {"fp64": hg.FP64, "mixed": hg.MIXED, "fp32": hg.FP32}[precision]
     ens = small_ensemble()
     b = hg.Batch([p for p, _ in ens], [q for _, q in ens], precision=prec)
     info = b.info()

@@ -174,7 +174,7 @@ def test_channel_mass_flux_parity(hg, oracle):
     assert abs(st["body_force_x"] - f_ref) <= tol_f
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_batch_mass_flux_members(hg, oracle, tmp_path, precision):
     """Batched members with the constant-mass-flux controller (two walled,
     stretched channels, one started from another force) beside a periodic
@@ -186,7 +186,7 @@ def test_batch_mass_flux_members(hg, oracle, tmp_path, precision):
 
     os.environ["HGKS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
     try:
-        prec = hg.FP64 if precision == "fp64" else hg.MIXED
+        prec = {"fp64": hg.FP64, "mixed": hg.MIXED, "fp32": hg.FP32}[precision]
         pa, qa = channel_case((16, 24, 12))
         pa["mass_flux_control"] = True
         pb, qb = channel_case((8, 16, 8))
