@@ -143,7 +143,7 @@ def ensemble_bench(steps: int, precision: str) -> dict:
     from paper_2207_01173_amd import hgks
     from paper_2207_01173_amd import workloads as W
 
-    prec = hgks.FP64 if precision == "fp64" else hgks.MIXED
+    prec = {"fp64": hgks.FP64, "mixed": hgks.MIXED, "fp32": hgks.FP32}[precision]
     params = W.tgv_ensemble(64)
     q0 = [W.tgv_initial(p) for p in params]
     cells = sum(p["n"][0] * p["n"][1] * p["n"][2] for p in params)
@@ -161,7 +161,9 @@ def ensemble_bench(steps: int, precision: str) -> dict:
     def instance_loop(stream):
         """Every instance advanced one step at a time in turn; on a created
         stream each hgks_step replays that instance's captured step, on the
-        default stream it launches the kernels one by one."""
+        default stream it launches the kernels one by one.  (Whole-code FP32:
+        each of these calls also rounds the state into the FP32 working copy
+        and writes it back, which the batch does once per call.)"""
         solvers = [hgks.Solver(p, q, precision=prec, stream=stream) for p, q in zip(params, q0)]
         for s in solvers:
             s.step(1, 0.0)
@@ -420,7 +422,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--repeats", type=int, default=5,
                     help="blocks of --steps steps timed on the FP64 path (the first gives value; all give the spread)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="precision of --ensemble")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "fp32"], default="fp64", help="precision of --ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed and FP32 runs beside FP64")
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid of the oracle's timed sample")
