@@ -1285,24 +1285,32 @@ __global__ __launch_bounds__(CELL_THREADS) void convert_kernel(const A* __restri
 // ---- statistics ----------------------------------------------------------
 enum { ST_EK = 0, ST_ENS, ST_DIL, ST_TOT, ST_MAX = ST_TOT + 5, ST_MINP = ST_MAX + 5, ST_MINR, ST_BAD, ST_COUNT };
 
-__device__ __forceinline__ double vel(const double* __restrict__ q, const Params& P, int comp, int i, int j, int k) {
+// Velocity U = m / rho of a padded-state cell (all three components from
+// one load of the cell).
+__device__ __forceinline__ void vel3(const double* __restrict__ q, const Params& P, int i, int j, int k,
+                                     double u[3]) {
   double v[5];
   load_cell(q, P, i, j, k, v);
-  return v[1 + comp] / v[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = v[1 + a] / v[0];
 }
 
-// Fourth-order central difference of U_comp along axis, in index space
-// scaled by d(index)/dx at the cell centre.
-__device__ __forceinline__ double dvel(const double* __restrict__ q, const Params& P, int comp, int axis, int i,
-                                       int j, int k) {
+// Fourth-order central differences of the three velocity components along
+// axis, in index space scaled by d(index)/dx at the cell centre: g[a] =
+// dU_a / dx_axis.
+__device__ __forceinline__ void dvel3(const double* __restrict__ q, const Params& P, int axis, int i, int j, int k,
+                                      double g[3]) {
   int o[3] = {0, 0, 0};
   o[axis] = 1;
-  double m2 = vel(q, P, comp, i - 2 * o[0], j - 2 * o[1], k - 2 * o[2]);
-  double m1 = vel(q, P, comp, i - o[0], j - o[1], k - o[2]);
-  double p1 = vel(q, P, comp, i + o[0], j + o[1], k + o[2]);
-  double p2 = vel(q, P, comp, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2]);
-  int ia = axis == 0 ? i : (axis == 1 ? j : k);
-  return (m2 - 8.0 * m1 + 8.0 * p1 - p2) / 12.0 * P.dcen[axis][ia];
+  double m2[3], m1[3], p1[3], p2[3];
+  vel3(q, P, i - 2 * o[0], j - 2 * o[1], k - 2 * o[2], m2);
+  vel3(q, P, i - o[0], j - o[1], k - o[2], m1);
+  vel3(q, P, i + o[0], j + o[1], k + o[2], p1);
+  vel3(q, P, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2], p2);
+  const int ia = axis == 0 ? i : (axis == 1 ? j : k);
+  const double sc = P.dcen[axis][ia];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g[a] = (m2[a] - 8.0 * m1[a] + 8.0 * p1[a] - p2[a]) / 12.0 * sc;
 }
 
 __global__ __launch_bounds__(CELL_THREADS) void stats_partial_kernel(const double* __restrict__ q, Params P,
@@ -1324,9 +1332,13 @@ __global__ __launch_bounds__(CELL_THREADS) void stats_partial_kernel(const doubl
     const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0];
     const double p = P.gm1 * (v[4] - ke);
     s[ST_EK] = ke * dv;
-    double gr[3][3];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) gr[a][b] = dvel(q, P, a, b, i, j, k);
+    double gr[3][3];  // gr[a][b] = dU_a / dx_b
+    for (int b = 0; b < 3; ++b) {
+      double g[3];
+      dvel3(q, P, b, i, j, k, g);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gr[a][b] = g[a];
+    }
     const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
     const double dv_ = gr[0][0] + gr[1][1] + gr[2][2];
     s[ST_ENS] = (wx * wx + wy * wy + wz * wz) * dv;
