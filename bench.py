@@ -42,7 +42,7 @@ UNIT = "cell-stage updates/s"
 # kernel sources they were measured on: `flop_counts_current` says whether the
 # sources still hash to those.
 FLUX_EXECUTED = {
-    "sources_sha256": "61c40b861dec3932bf9619baadb162cc657adbaa8c6108a0d75a1de92e0829d6",
+    "sources_sha256": "c9f871e43af83b38794e06aae81882f87da46814f9d4100844b91d553f293832",
     "fp64_flop_per_gp": 3936.0,   # FP64 flux kernels (their FP32 operations: 4-6 per lane)
     "fp32_flop_per_gp": 3652.0,   # FP32 flux kernel of the mixed path (plus 23 FP64 per lane)
 }
@@ -59,8 +59,8 @@ ALGORITHMIC_BYTES_PER_CELL_STAGE = 120.0
 # Mean of the three FP64 directions:
 TRAFFIC_MEASURED = {
     "n": 256,
-    "sources_sha256": "61c40b861dec3932bf9619baadb162cc657adbaa8c6108a0d75a1de92e0829d6",
-    "fetch_bytes": 9.4035e+09,
+    "sources_sha256": "c9f871e43af83b38794e06aae81882f87da46814f9d4100844b91d553f293832",
+    "fetch_bytes": 9.4032e+09,
     "write_bytes": 1.3422e+09,
 }
 
